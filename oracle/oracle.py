@@ -1,0 +1,214 @@
+"""ctypes front end of the CPU FP64 oracle (``oracle/libbdo.so``).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this module.  It shares no
+code with the HIP library or its Python binding.
+
+Every function mirrors one routine of ``oracle/bdo.c``; the equations each
+follows are cited there (arXiv 2208.06559, Sections 3-4).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbdo.so")
+
+OK, ERR_PARAM, ERR_NOT_SPD, ERR_NO_CONVERGE = 0, 1, 2, 3
+NOISE_GAUSSIAN, NOISE_UNIFORM_PAPER = 0, 1
+FILL_LOWER, FILL_FULL = 0, 1
+
+
+def build(verbose: bool = False) -> str:
+    """Compile ``bdo.c`` into ``libbdo.so`` with gcc (OpenMP, FP64)."""
+    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-Wall", "-Wextra", "-o", LIB_PATH + ".tmp", os.path.join(HERE, "bdo.c"), "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n_beads", C.c_int32),
+        ("noise", C.c_int32),
+        ("b", C.c_double),
+        ("hstar", C.c_double),
+        ("a", C.c_double),
+        ("dt", C.c_double),
+        ("kappa", C.c_double * 9),
+        ("seed", C.c_uint64),
+        ("chain_id", C.c_uint64),
+        ("newton_tol", C.c_double),
+        ("newton_maxit", C.c_int32),
+        ("pad_", C.c_int32),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32),
+        ("newton_iters", C.c_int32),
+        ("potrf_info", C.c_int64),
+        ("max_rod_err", C.c_double),
+        ("last_newton_res", C.c_double),
+        ("krylov_iters", C.c_int32),
+        ("pad_", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"oracle library missing: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        u64p = C.POINTER(C.c_uint64)
+        pp = C.POINTER(Params)
+        ip = C.POINTER(Info)
+        L.bdo_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.bdo_philox4x64_10.restype = None
+        L.bdo_noise.argtypes = [pp, C.c_int64, C.c_int64, dp]
+        L.bdo_noise.restype = None
+        L.bdo_rpy_block.argtypes = [C.c_double, C.c_double, dp, dp]
+        L.bdo_rpy_block.restype = None
+        L.bdo_rpy_assemble.argtypes = [pp, dp, dp, C.c_int64, C.c_int32]
+        L.bdo_rpy_assemble.restype = C.c_int
+        L.bdo_cholesky.argtypes = [C.c_int64, dp, C.c_int64]
+        L.bdo_cholesky.restype = C.c_int64
+        L.bdo_brownian.argtypes = [pp, C.c_int64, dp, C.c_int64, dp, dp]
+        L.bdo_brownian.restype = C.c_int
+        for name in ("bdo_constrain", "bdo_constrain_dense"):
+            f = getattr(L, name)
+            f.argtypes = [pp, dp, dp, dp, ip]
+            f.restype = C.c_int
+        L.bdo_step.argtypes = [pp, C.c_int64, dp, ip]
+        L.bdo_step.restype = C.c_int
+        L.bdo_run.argtypes = [pp, C.c_int64, C.c_int64, dp, ip]
+        L.bdo_run.restype = C.c_int
+        L.bdo_run_many.argtypes = [pp, C.c_int32, u64p, C.c_int64, C.c_int64, dp,
+                                   C.POINTER(C.c_int32)]
+        L.bdo_run_many.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(n_beads: int, *, b=1.0, hstar=0.25, a=0.5, dt=1e-4, kappa=None, seed=0,
+                chain_id=0, noise=NOISE_GAUSSIAN, newton_tol=1e-13, newton_maxit=20) -> Params:
+    p = Params()
+    p.n_beads = int(n_beads)
+    p.noise = int(noise)
+    p.b, p.hstar, p.a, p.dt = float(b), float(hstar), float(a), float(dt)
+    k = np.zeros(9) if kappa is None else np.asarray(kappa, dtype=np.float64).reshape(9)
+    for e in range(9):
+        p.kappa[e] = float(k[e])
+    p.seed = int(seed) & (2**64 - 1)
+    p.chain_id = int(chain_id) & (2**64 - 1)
+    p.newton_tol = float(newton_tol)
+    p.newton_maxit = int(newton_maxit)
+    return p
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, dtype=np.uint64)
+    k = np.asarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    u64p = C.POINTER(C.c_uint64)
+    lib().bdo_philox4x64_10(c.ctypes.data_as(u64p), k.ctypes.data_as(u64p), out.ctypes.data_as(u64p))
+    return out
+
+
+def noise(p: Params, step: int, n: int) -> np.ndarray:
+    xi = np.zeros(n)
+    lib().bdo_noise(C.byref(p), step, n, _dp(xi))
+    return xi
+
+
+def rpy_block(hstar: float, a: float, Rvec) -> np.ndarray:
+    R = np.ascontiguousarray(Rvec, dtype=np.float64)
+    out = np.zeros(9)
+    lib().bdo_rpy_block(hstar, a, _dp(R), _dp(out))
+    return out.reshape(3, 3)
+
+
+def rpy_assemble(p: Params, x: np.ndarray, fill: int = FILL_FULL, ld: int | None = None) -> np.ndarray:
+    """Returns D as an (n x n) Fortran-ordered array (column-major, ld = n)."""
+    n = 3 * p.n_beads
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    assert x.shape == (p.n_beads, 3)
+    D = np.zeros((n, n), dtype=np.float64, order="F")
+    st = lib().bdo_rpy_assemble(C.byref(p), _dp(x), _dp(D), n, fill)
+    if st != OK:
+        raise ValueError(f"bdo_rpy_assemble status {st}")
+    return D
+
+
+def cholesky(A: np.ndarray) -> tuple[np.ndarray, int]:
+    """Lower Cholesky of the lower triangle of A; returns (L, info) with
+    the strict upper triangle of the input copied through untouched."""
+    L = np.array(A, dtype=np.float64, order="F", copy=True)
+    n = L.shape[0]
+    info = lib().bdo_cholesky(n, _dp(L), n)
+    return L, int(info)
+
+
+def brownian(p: Params, step: int, L: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    n = 3 * p.n_beads
+    Lf = np.asfortranarray(L, dtype=np.float64)
+    y = np.zeros(n)
+    xi = np.zeros(n)
+    st = lib().bdo_brownian(C.byref(p), step, _dp(Lf), n, _dp(y), _dp(xi))
+    if st != OK:
+        raise ValueError(f"bdo_brownian status {st}")
+    return y, xi
+
+
+def constrain(p: Params, x_old: np.ndarray, x_pred: np.ndarray, dense: bool = False):
+    xo = np.ascontiguousarray(x_old, dtype=np.float64)
+    xs = np.array(x_pred, dtype=np.float64, order="C", copy=True)
+    T = np.zeros(max(p.n_beads - 1, 0))
+    info = Info()
+    f = lib().bdo_constrain_dense if dense else lib().bdo_constrain
+    f(C.byref(p), _dp(xo), _dp(xs), _dp(T), C.byref(info))
+    return xs, T, info.as_dict()
+
+
+def step(p: Params, s: int, x: np.ndarray):
+    xx = np.array(x, dtype=np.float64, order="C", copy=True)
+    info = Info()
+    lib().bdo_step(C.byref(p), s, _dp(xx), C.byref(info))
+    return xx, info.as_dict()
+
+
+def run(p: Params, step0: int, nsteps: int, x: np.ndarray):
+    xx = np.array(x, dtype=np.float64, order="C", copy=True)
+    info = Info()
+    lib().bdo_run(C.byref(p), step0, nsteps, _dp(xx), C.byref(info))
+    return xx, info.as_dict()
+
+
+def run_many(p: Params, chain_ids, step0: int, nsteps: int, X: np.ndarray):
+    """X: (nchains, N, 3), advanced in place on a copy; returns (X, status)."""
+    XX = np.array(X, dtype=np.float64, order="C", copy=True)
+    ids = np.ascontiguousarray(chain_ids, dtype=np.uint64)
+    st = np.zeros(len(ids), dtype=np.int32)
+    lib().bdo_run_many(C.byref(p), len(ids), ids.ctypes.data_as(C.POINTER(C.c_uint64)), step0,
+                       nsteps, _dp(XX), st.ctypes.data_as(C.POINTER(C.c_int32)))
+    return XX, st
