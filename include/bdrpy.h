@@ -1,0 +1,166 @@
+/*
+ * bdrpy.h -- C ABI of libbdrpy, the MI355X (gfx950) hot path of bead-rod
+ * Brownian dynamics with Rotne-Prager-Yamakawa hydrodynamic interactions
+ * (arXiv 2208.06559).
+ *
+ * One timestep of one chain (Section 3, Eq. 6 with Eqs. 7-10; the per-step
+ * order of Section 4's flowchart):
+ *   1. bd_rpy_assemble  D = D(x), the 3N x 3N RPY diffusion tensor
+ *   2. bd_cholesky      D = B B^T, B lower (in place)
+ *   3. bd_brownian      y = c_B B xi, xi from a counter-based Philox stream
+ *   4. predictor        x* = x + dt kappa.x + y       (inside bd_step)
+ *   5. bd_constrain     rod tensions T with |Q_k| = b, then x^{t+dt}
+ *   bd_step runs 1-5 on the handle's stream.
+ *
+ * Conventions shared by every entry point
+ *   - N beads (the paper's beads 0..N are N+1 beads; here N counts beads),
+ *     N-1 rods Q_k = r_{k+1} - r_k, matrix order n = 3N.
+ *   - Scalar index e = 3i + alpha (bead-major, component-minor), the block
+ *     layout of the paper's two-bead example (Section 4, Eqs. 18-20).
+ *   - Positions x: row-major N x 3 doubles.  Matrices: column-major with
+ *     leading dimension ld >= n, FP64.
+ *   - Units zeta = kT = 1 (so D_ii = I, Eq. 7); lengths in Kuhn steps b.
+ *   - Pointers named d_* are device pointers, caller-owned; the library never
+ *     allocates or frees caller buffers.  Scratch memory is the caller's
+ *     workspace, sized by bd_workspace_size.  The handle owns only a few
+ *     bytes of device state (status word, Newton state).
+ *   - Calls are asynchronous on the handle's stream.  Argument errors are
+ *     returned synchronously; numerical errors (non-positive pivot, Newton
+ *     non-convergence) are recorded in device memory and reported by
+ *     bd_get_info, which synchronises the stream.  On an error return the
+ *     outputs are unspecified, but no write goes outside the caller's
+ *     buffers.  No C++ exception crosses this interface.
+ *   - Results are bitwise reproducible run to run on one GPU (no floating
+ *     point atomics).  A handle must not be used from two host threads at
+ *     once.
+ */
+#ifndef BDRPY_H
+#define BDRPY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BD_OK = 0,
+  BD_ERR_PARAM = 1,       /* invalid argument (null pointer, size, range)      */
+  BD_ERR_NOT_SPD = 2,     /* non-positive pivot in the Cholesky factorisation  */
+  BD_ERR_NO_CONVERGE = 3, /* tension Newton did not reach newton_tol           */
+  BD_ERR_HIP = 4,         /* a HIP runtime call failed                         */
+  BD_ERR_ALLOC = 5,       /* the handle's own small allocation failed          */
+  BD_ERR_UNSUPPORTED = 6  /* device is not gfx950                              */
+} bd_status_t;
+
+typedef enum {
+  BD_PREC_FP64 = 0, /* every step in FP64                                       */
+  BD_PREC_MIXED = 1 /* Cholesky trailing updates on FP32 MFMA with FP32
+                       accumulation into FP64 storage; diagonal blocks, panel
+                       solves, noise and the tension solve stay FP64          */
+} bd_precision_t;
+
+typedef enum {
+  BD_NOISE_GAUSSIAN = 0,     /* xi ~ N(0,1), y = sqrt(2 dt) B xi               */
+  BD_NOISE_UNIFORM_PAPER = 1 /* n uniform on [-1,1] (Eq. 2), y = sqrt(6 dt) B n */
+} bd_noise_t;
+
+typedef enum { BD_FILL_LOWER = 0, BD_FILL_FULL = 1 } bd_fill_t;
+
+typedef enum {
+  BD_OP_CHOLESKY = 0,
+  BD_OP_BROWNIAN = 1,
+  BD_OP_CONSTRAIN = 2,
+  BD_OP_STEP = 3
+} bd_op_t;
+
+/* Model and step parameters (Sections 3 and 5). */
+typedef struct {
+  int32_t n_beads;      /* N >= 2                                             */
+  int32_t noise;        /* bd_noise_t                                          */
+  double b;             /* rod length, > 0                                     */
+  double hstar;         /* HI strength h* of Eqs. 8-9, 0 <= h* <= a (0: HI off) */
+  double a;             /* bead radius of Eqs. 8-9, > 0                        */
+  double dt;            /* timestep, > 0                                       */
+  double kappa[9];      /* row-major (grad v)^T, flow velocity v = kappa . r (Eq. 5) */
+  uint64_t seed;        /* Philox4x64-10 key word 0                            */
+  uint64_t chain_id;    /* Philox4x64-10 key word 1                            */
+  double newton_tol;    /* stop when max_k | |Q_k|/b - 1 | <= newton_tol        */
+  int32_t newton_maxit; /* >= 1, Newton steps before BD_ERR_NO_CONVERGE        */
+  int32_t reserved;     /* must be 0                                           */
+} bd_params_t;
+
+/* Result of the most recent call on a handle. */
+typedef struct {
+  int32_t status;         /* bd_status_t                                      */
+  int32_t newton_iters;   /* Newton steps performed by the last constraint    */
+  int64_t potrf_info;     /* 0, or 1-based column of the first non-positive pivot */
+  double max_rod_err;     /* max_k | |Q_k|/b - 1 | after the last constraint  */
+  double last_newton_res; /* max_k | |Q_k|^2 - b^2 | at the last Newton check */
+  int32_t krylov_iters;   /* GMRES iterations summed over those Newton steps  */
+  int32_t reserved;
+} bd_info_t;
+
+typedef struct bd_handle_s* bd_handle_t;
+
+/* Create a handle on HIP device `device` that launches on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Fails with BD_ERR_UNSUPPORTED
+ * unless the device is gfx950. */
+bd_status_t bd_create(bd_handle_t* h, int device, void* hip_stream);
+bd_status_t bd_destroy(bd_handle_t h);
+bd_status_t bd_set_stream(bd_handle_t h, void* hip_stream);
+
+/* Bytes of device workspace the operation needs for matrix order n = 3N
+ * (for BD_OP_CHOLESKY, n is the matrix order of the call). */
+bd_status_t bd_workspace_size(bd_op_t op, int64_t n, bd_precision_t prec, size_t* bytes);
+
+/* D(x) per Eqs. 7-9: D_ii = I; for i != j with R = r_i - r_j, |R| >= 2a the
+ * far-field block (Eq. 8), else the near-field block (Eq. 9).
+ * d_x: N x 3; d_D: n x n column-major, ld >= n.  BD_FILL_LOWER writes the
+ * lower triangle including the diagonal and leaves the rest untouched;
+ * BD_FILL_FULL writes every element. */
+bd_status_t bd_rpy_assemble(bd_handle_t h, const bd_params_t* p, const double* d_x, double* d_D,
+                            int64_t ld, bd_fill_t fill);
+
+/* In-place Cholesky D = B B^T (Eq. 10) of the lower triangle of d_A
+ * (n x n column-major, ld >= n); B overwrites the lower triangle, the strict
+ * upper triangle is not touched.  Blocked right-looking: FP64 diagonal
+ * blocks and panel solves; trailing updates on MFMA in FP64 or (MIXED) FP32.
+ * d_ws: workspace of bd_workspace_size(BD_OP_CHOLESKY, n, prec) bytes.
+ * A non-positive pivot sets potrf_info (see bd_get_info). */
+bd_status_t bd_cholesky(bd_handle_t h, int64_t n, double* d_A, int64_t ld, bd_precision_t prec,
+                        void* d_ws, size_t ws_bytes);
+
+/* y = c_B B xi: the Brownian term of Eq. 6 times dt.  xi_e for e = 3i+alpha
+ * comes from Philox4x64-10 with key (seed, chain_id) and counter
+ * (e/4, step, 0, 0), lane e%4; Gaussian by Box-Muller on lane pairs
+ * (0,1), (2,3), or 2u-1 in the paper's uniform mode.  d_L: the lower
+ * triangle of B (n x n, ld >= n); d_y: n; d_xi_out: n or NULL. */
+bd_status_t bd_brownian(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_L,
+                        int64_t ld, double* d_y, double* d_xi_out, void* d_ws, size_t ws_bytes);
+
+/* Rigid-rod constraint: tensions T_k along the rod directions u_k of d_x_old
+ * such that x^{t+dt} = x* - dt D(x_old) Delta^T U T has |Q_k| = b for every
+ * rod (the infinite-stiffness limit of the semi-implicit spring update of
+ * Eqs. 13-17, every tension coupled through the full D of Eqs. 7-9).
+ * Inexact Newton from T = 0; each correction by GMRES right-preconditioned
+ * with the tridiagonal part of the Jacobian; products with D are
+ * matrix-free.  d_x_pred_inout: x* in, x^{t+dt} out (N x 3); d_T_out: N-1
+ * or NULL.  N <= 4097 (BD_ERR_UNSUPPORTED above).  The call synchronises
+ * the stream a few times to stop the iteration once it has converged. */
+bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_old,
+                         double* d_x_pred_inout, double* d_T_out, void* d_ws, size_t ws_bytes);
+
+/* One timestep of one chain: steps 1-5 above with noise counter `step`.
+ * d_x_inout: N x 3, advanced in place. */
+bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d_x_inout,
+                    bd_precision_t prec, void* d_ws, size_t ws_bytes);
+
+/* Synchronise the handle's stream and return the info of the last call. */
+bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDRPY_H */

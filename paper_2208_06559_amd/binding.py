@@ -1,0 +1,231 @@
+"""ctypes binding of ``libbdrpy.so`` (see ``include/bdrpy.h``).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of the library.  PyTorch supplies device memory (tensors) and the
+current HIP stream.  Calls fail loudly when the library is missing or the
+device is not an MI355X (gfx950); there is no CPU fallback.
+
+Matrices are column-major with leading dimension ``ld``: a buffer for an
+n x n matrix is a float64 tensor of shape (n, ld) whose row c holds column c
+(use :func:`matrix_view` to see it as an ordinary n x n matrix).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbdrpy.so")
+
+OK, ERR_PARAM, ERR_NOT_SPD, ERR_NO_CONVERGE, ERR_HIP, ERR_ALLOC, ERR_UNSUPPORTED = range(7)
+PREC_FP64, PREC_MIXED = 0, 1
+NOISE_GAUSSIAN, NOISE_UNIFORM_PAPER = 0, 1
+FILL_LOWER, FILL_FULL = 0, 1
+OP_CHOLESKY, OP_BROWNIAN, OP_CONSTRAIN, OP_STEP = 0, 1, 2, 3
+
+STATUS_NAMES = {0: "BD_OK", 1: "BD_ERR_PARAM", 2: "BD_ERR_NOT_SPD", 3: "BD_ERR_NO_CONVERGE",
+                4: "BD_ERR_HIP", 5: "BD_ERR_ALLOC", 6: "BD_ERR_UNSUPPORTED"}
+
+EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_rpy_assemble",
+           "bd_cholesky", "bd_brownian", "bd_constrain", "bd_step", "bd_get_info")
+
+
+class BdError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}")
+        self.status = status
+
+
+class Params(C.Structure):
+    """Mirror of bd_params_t."""
+    _fields_ = [
+        ("n_beads", C.c_int32),
+        ("noise", C.c_int32),
+        ("b", C.c_double),
+        ("hstar", C.c_double),
+        ("a", C.c_double),
+        ("dt", C.c_double),
+        ("kappa", C.c_double * 9),
+        ("seed", C.c_uint64),
+        ("chain_id", C.c_uint64),
+        ("newton_tol", C.c_double),
+        ("newton_maxit", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+class Info(C.Structure):
+    """Mirror of bd_info_t."""
+    _fields_ = [
+        ("status", C.c_int32),
+        ("newton_iters", C.c_int32),
+        ("potrf_info", C.c_int64),
+        ("max_rod_err", C.c_double),
+        ("last_newton_res", C.c_double),
+        ("krylov_iters", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+def make_params(n_beads: int, *, b=1.0, hstar=0.25, a=0.5, dt=1e-4, kappa=None, seed=0,
+                chain_id=0, noise=NOISE_GAUSSIAN, newton_tol=1e-13, newton_maxit=20) -> Params:
+    p = Params()
+    p.n_beads = int(n_beads)
+    p.noise = int(noise)
+    p.b, p.hstar, p.a, p.dt = float(b), float(hstar), float(a), float(dt)
+    k = np.zeros(9) if kappa is None else np.asarray(kappa, dtype=np.float64).reshape(9)
+    for e in range(9):
+        p.kappa[e] = float(k[e])
+    p.seed = int(seed) & (2**64 - 1)
+    p.chain_id = int(chain_id) & (2**64 - 1)
+    p.newton_tol = float(newton_tol)
+    p.newton_maxit = int(newton_maxit)
+    p.reserved = 0
+    return p
+
+
+_lib = None
+
+
+def lib():
+    """Load libbdrpy.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH}; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, pp = C.c_void_p, C.c_void_p, C.POINTER(Params)
+        L.bd_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+        L.bd_destroy.argtypes = [vp]
+        L.bd_set_stream.argtypes = [vp, vp]
+        L.bd_workspace_size.argtypes = [C.c_int, C.c_int64, C.c_int, C.POINTER(C.c_size_t)]
+        L.bd_rpy_assemble.argtypes = [vp, pp, dp, dp, C.c_int64, C.c_int]
+        L.bd_cholesky.argtypes = [vp, C.c_int64, dp, C.c_int64, C.c_int, vp, C.c_size_t]
+        L.bd_brownian.argtypes = [vp, pp, C.c_int64, dp, C.c_int64, dp, dp, vp, C.c_size_t]
+        L.bd_constrain.argtypes = [vp, pp, dp, dp, dp, vp, C.c_size_t]
+        L.bd_step.argtypes = [vp, pp, C.c_int64, dp, C.c_int, vp, C.c_size_t]
+        L.bd_get_info.argtypes = [vp, C.POINTER(Info)]
+        for name in EXPORTS:
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != OK:
+        raise BdError(st, where)
+
+
+def _dev_f64(t: torch.Tensor, name: str, numel: int | None = None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a CUDA/HIP tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name}: expected float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: needs {numel} elements, has {t.numel()}")
+    return t.data_ptr()
+
+
+def workspace_size(op: int, n: int, prec: int = PREC_FP64) -> int:
+    out = C.c_size_t(0)
+    _check(lib().bd_workspace_size(op, n, prec, C.byref(out)), "bd_workspace_size")
+    return int(out.value)
+
+
+def matrix_view(buf: torch.Tensor, n: int) -> torch.Tensor:
+    """n x n matrix view of a column-major (n, ld) buffer."""
+    return buf[:n, :n].t()
+
+
+class Handle:
+    """One bd_handle_t on the current device, launching on torch's current
+    stream at the time of each call."""
+
+    def __init__(self, device: int | None = None):
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.device = dev
+        h = C.c_void_p()
+        with torch.cuda.device(dev):
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(lib().bd_create(C.byref(h), dev, C.c_void_p(stream)), "bd_create")
+        self._h = h
+        self._ws = {}
+
+    def close(self):
+        if self._h:
+            lib().bd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        lib().bd_set_stream(self._h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def workspace(self, op: int, n: int, prec: int = PREC_FP64) -> torch.Tensor:
+        nbytes = workspace_size(op, n, prec)
+        key = (op, n, prec)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+            self._ws[key] = ws
+        return ws
+
+    def rpy_assemble(self, p: Params, x: torch.Tensor, D: torch.Tensor, ld: int,
+                     fill: int = FILL_LOWER):
+        n = 3 * p.n_beads
+        self._sync_stream()
+        _check(lib().bd_rpy_assemble(self._h, C.byref(p), _dev_f64(x, "x", n),
+                                     _dev_f64(D, "D", (n - 1) * ld + n), ld, fill),
+               "bd_rpy_assemble")
+
+    def cholesky(self, A: torch.Tensor, n: int, ld: int, prec: int = PREC_FP64,
+                 ws: torch.Tensor | None = None):
+        ws = self.workspace(OP_CHOLESKY, n, prec) if ws is None else ws
+        self._sync_stream()
+        _check(lib().bd_cholesky(self._h, n, _dev_f64(A, "A", (n - 1) * ld + n), ld, prec,
+                                 ws.data_ptr(), ws.numel() * ws.element_size()), "bd_cholesky")
+
+    def brownian(self, p: Params, step: int, L: torch.Tensor, ld: int, y: torch.Tensor,
+                 xi_out: torch.Tensor | None = None):
+        n = 3 * p.n_beads
+        ws = self.workspace(OP_BROWNIAN, n)
+        self._sync_stream()
+        xi_ptr = _dev_f64(xi_out, "xi_out", n) if xi_out is not None else None
+        _check(lib().bd_brownian(self._h, C.byref(p), step, _dev_f64(L, "L", (n - 1) * ld + n), ld,
+                                 _dev_f64(y, "y", n), xi_ptr, ws.data_ptr(), ws.numel()),
+               "bd_brownian")
+
+    def constrain(self, p: Params, x_old: torch.Tensor, x_pred: torch.Tensor,
+                  T_out: torch.Tensor | None = None):
+        n = 3 * p.n_beads
+        ws = self.workspace(OP_CONSTRAIN, n)
+        self._sync_stream()
+        t_ptr = _dev_f64(T_out, "T_out", p.n_beads - 1) if T_out is not None else None
+        _check(lib().bd_constrain(self._h, C.byref(p), _dev_f64(x_old, "x_old", n),
+                                  _dev_f64(x_pred, "x_pred", n), t_ptr, ws.data_ptr(),
+                                  ws.numel()), "bd_constrain")
+
+    def step(self, p: Params, step: int, x: torch.Tensor, prec: int = PREC_FP64,
+             ws: torch.Tensor | None = None):
+        n = 3 * p.n_beads
+        ws = self.workspace(OP_STEP, n, prec) if ws is None else ws
+        self._sync_stream()
+        _check(lib().bd_step(self._h, C.byref(p), step, _dev_f64(x, "x", n), prec, ws.data_ptr(),
+                             ws.numel() * ws.element_size()), "bd_step")
+
+    def info(self) -> dict:
+        out = Info()
+        _check(lib().bd_get_info(self._h, C.byref(out)), "bd_get_info")
+        return out.as_dict()

@@ -1,0 +1,262 @@
+// C ABI of libbdrpy: handle, argument checks, workspace carving and the
+// per-step orchestration (assemble -> Cholesky -> noise -> predictor ->
+// constraint), all on the handle's stream.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.hpp"
+
+namespace bd {
+int constrain_max_beads();
+}
+
+struct bd_handle_s {
+  int device;
+  hipStream_t stream;
+  bd::DevState* st;    // device
+  bd::DevState* host;  // pinned host mirror
+};
+
+namespace {
+
+using bd::DevState;
+
+bool params_ok(const bd_params_t* p) {
+  if (!p) return false;
+  if (p->n_beads < 2) return false;
+  if (!(p->b > 0.0) || !isfinite(p->b)) return false;
+  if (!(p->a > 0.0) || !isfinite(p->a)) return false;
+  if (!(p->dt > 0.0) || !isfinite(p->dt)) return false;
+  if (!(p->hstar >= 0.0) || !(p->hstar <= p->a)) return false;
+  if (p->noise != BD_NOISE_GAUSSIAN && p->noise != BD_NOISE_UNIFORM_PAPER) return false;
+  if (!(p->newton_tol > 0.0) || !isfinite(p->newton_tol)) return false;
+  if (p->newton_maxit < 1) return false;
+  if (p->reserved != 0) return false;
+  for (int e = 0; e < 9; ++e)
+    if (!isfinite(p->kappa[e])) return false;
+  return true;
+}
+
+bool prec_ok(bd_precision_t prec) { return prec == BD_PREC_FP64 || prec == BD_PREC_MIXED; }
+
+// Leading dimension of the internal D in bd_step: a multiple of 64 doubles.
+int64_t step_ld(int64_t n) { return (n + 63) / 64 * 64; }
+
+struct StepLayout {
+  size_t d, chol, brown, cons, y, xs, total;
+};
+
+StepLayout step_layout(int64_t n, bd_precision_t prec) {
+  StepLayout L;
+  size_t off = 0;
+  L.d = off;
+  off += bd::align_up(sizeof(double) * (size_t)step_ld(n) * (size_t)n, 256);
+  L.chol = off;
+  off += bd::align_up(bd::cholesky_workspace_bytes(n, prec), 256);
+  L.brown = off;
+  off += bd::align_up(bd::brownian_workspace_bytes(n), 256);
+  L.cons = off;
+  off += bd::align_up(bd::constrain_workspace_bytes(n / 3), 256);
+  L.y = off;
+  off += bd::align_up(sizeof(double) * n, 256);
+  L.xs = off;
+  off += bd::align_up(sizeof(double) * n, 256);
+  L.total = off;
+  return L;
+}
+
+__global__ void reset_state_kernel(DevState* st) {
+  st->status = BD_OK;
+  st->newton_iters = 0;
+  st->potrf_info = 0;
+  st->max_rod_err = 0.0;
+  st->last_newton_res = 0.0;
+  st->krylov_iters = 0;
+  st->done = 0;
+}
+
+// x <- xs unless the factorisation failed (positions stay at x^t then).
+__global__ void commit_positions_kernel(double* x, const double* xs, int64_t n,
+                                        const DevState* st) {
+  if (st->status == BD_ERR_NOT_SPD) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] = xs[e];
+}
+
+bd_status_t hip_status(hipError_t e) { return e == hipSuccess ? BD_OK : BD_ERR_HIP; }
+
+bd_status_t enter(bd_handle_t h) {
+  if (!h) return BD_ERR_PARAM;
+  return hip_status(hipSetDevice(h->device));
+}
+
+hipError_t reset(bd_handle_t h) {
+  hipLaunchKernelGGL(reset_state_kernel, dim3(1), dim3(1), 0, h->stream, h->st);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
+  if (!out) return BD_ERR_PARAM;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return BD_ERR_HIP;
+  if (device < 0 || device >= count) return BD_ERR_PARAM;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return BD_ERR_HIP;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BD_ERR_UNSUPPORTED;
+  if (hipSetDevice(device) != hipSuccess) return BD_ERR_HIP;
+  bd_handle_s* h = new (std::nothrow) bd_handle_s;
+  if (!h) return BD_ERR_ALLOC;
+  h->device = device;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->st = nullptr;
+  h->host = nullptr;
+  if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
+      hipHostMalloc(&h->host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+    if (h->st) (void)hipFree(h->st);
+    delete h;
+    return BD_ERR_ALLOC;
+  }
+  memset(h->host, 0, sizeof(DevState));
+  if (hipMemcpy(h->st, h->host, sizeof(DevState), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(h->st);
+    (void)hipHostFree(h->host);
+    delete h;
+    return BD_ERR_HIP;
+  }
+  *out = h;
+  return BD_OK;
+}
+
+bd_status_t bd_destroy(bd_handle_t h) {
+  if (!h) return BD_ERR_PARAM;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(h->st);
+  (void)hipHostFree(h->host);
+  delete h;
+  return BD_OK;
+}
+
+bd_status_t bd_set_stream(bd_handle_t h, void* hip_stream) {
+  if (!h) return BD_ERR_PARAM;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  return BD_OK;
+}
+
+bd_status_t bd_workspace_size(bd_op_t op, int64_t n, bd_precision_t prec, size_t* bytes) {
+  if (!bytes || n < 1 || !prec_ok(prec)) return BD_ERR_PARAM;
+  switch (op) {
+    case BD_OP_CHOLESKY:
+      *bytes = bd::cholesky_workspace_bytes(n, prec);
+      return BD_OK;
+    case BD_OP_BROWNIAN:
+      if (n % 3) return BD_ERR_PARAM;
+      *bytes = bd::brownian_workspace_bytes(n);
+      return BD_OK;
+    case BD_OP_CONSTRAIN:
+      if (n % 3 || n < 6) return BD_ERR_PARAM;
+      *bytes = bd::constrain_workspace_bytes(n / 3);
+      return BD_OK;
+    case BD_OP_STEP:
+      if (n % 3 || n < 6) return BD_ERR_PARAM;
+      *bytes = step_layout(n, prec).total;
+      return BD_OK;
+  }
+  return BD_ERR_PARAM;
+}
+
+bd_status_t bd_rpy_assemble(bd_handle_t h, const bd_params_t* p, const double* d_x, double* d_D,
+                            int64_t ld, bd_fill_t fill) {
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!params_ok(p) || !d_x || !d_D) return BD_ERR_PARAM;
+  const int64_t n = 3 * (int64_t)p->n_beads;
+  if (ld < n || (fill != BD_FILL_LOWER && fill != BD_FILL_FULL)) return BD_ERR_PARAM;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
+  return hip_status(bd::launch_rpy_assemble(h->stream, *p, d_x, d_D, ld, fill));
+}
+
+bd_status_t bd_cholesky(bd_handle_t h, int64_t n, double* d_A, int64_t ld, bd_precision_t prec,
+                        void* d_ws, size_t ws_bytes) {
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (n < 1 || !d_A || ld < n || !prec_ok(prec) || !d_ws) return BD_ERR_PARAM;
+  if (ws_bytes < bd::cholesky_workspace_bytes(n, prec)) return BD_ERR_PARAM;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
+  return hip_status(bd::launch_cholesky(h->stream, n, d_A, ld, prec, d_ws, h->st));
+}
+
+bd_status_t bd_brownian(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_L,
+                        int64_t ld, double* d_y, double* d_xi_out, void* d_ws, size_t ws_bytes) {
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!params_ok(p) || !d_L || !d_y || !d_ws) return BD_ERR_PARAM;
+  const int64_t n = 3 * (int64_t)p->n_beads;
+  if (ld < n || ws_bytes < bd::brownian_workspace_bytes(n)) return BD_ERR_PARAM;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
+  return hip_status(bd::launch_brownian(h->stream, *p, step, d_L, ld, d_y, d_xi_out, d_ws));
+}
+
+bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_old,
+                         double* d_x_pred_inout, double* d_T_out, void* d_ws, size_t ws_bytes) {
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!params_ok(p) || !d_x_old || !d_x_pred_inout || !d_ws) return BD_ERR_PARAM;
+  if (p->n_beads > bd::constrain_max_beads()) return BD_ERR_UNSUPPORTED;
+  if (ws_bytes < bd::constrain_workspace_bytes(p->n_beads)) return BD_ERR_PARAM;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
+  return hip_status(bd::launch_constrain(h->stream, *p, d_x_old, d_x_pred_inout, d_T_out, d_ws,
+                                         h->st, h->host));
+}
+
+bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d_x,
+                    bd_precision_t prec, void* d_ws, size_t ws_bytes) {
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!params_ok(p) || !d_x || !d_ws || !prec_ok(prec)) return BD_ERR_PARAM;
+  if (p->n_beads > bd::constrain_max_beads()) return BD_ERR_UNSUPPORTED;
+  const int64_t n = 3 * (int64_t)p->n_beads;
+  const StepLayout L = step_layout(n, prec);
+  if (ws_bytes < L.total) return BD_ERR_PARAM;
+  char* base = static_cast<char*>(d_ws);
+  double* D = reinterpret_cast<double*>(base + L.d);
+  double* y = reinterpret_cast<double*>(base + L.y);
+  double* xs = reinterpret_cast<double*>(base + L.xs);
+  const int64_t ld = step_ld(n);
+  hipStream_t s = h->stream;
+  hipError_t he = reset(h);
+  if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
+  if (he == hipSuccess) he = bd::launch_cholesky(s, n, D, ld, prec, base + L.chol, h->st);
+  if (he == hipSuccess)
+    he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
+  if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);
+  if (he == hipSuccess)
+    he = bd::launch_constrain(s, *p, d_x, xs, nullptr, base + L.cons, h->st, h->host);
+  if (he == hipSuccess) {
+    hipLaunchKernelGGL(commit_positions_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       s, d_x, xs, n, h->st);
+    he = hipGetLastError();
+  }
+  return hip_status(he);
+}
+
+bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out) {
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!out) return BD_ERR_PARAM;
+  if (hipMemcpyAsync(h->host, h->st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream) !=
+      hipSuccess)
+    return BD_ERR_HIP;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return BD_ERR_HIP;
+  memcpy(out, h->host, sizeof(bd_info_t));
+  return BD_OK;
+}
+
+}  // extern "C"

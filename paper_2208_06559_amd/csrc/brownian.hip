@@ -1,0 +1,139 @@
+// Correlated Brownian displacement y = c_B * B * xi (the noise term of
+// Eq. 6 times dt) and the explicit predictor x* = x + dt kappa.x + y.
+//
+// xi is drawn in-kernel from Philox4x64-10 (one counter block per four
+// elements).  The lower-triangular matrix-vector product reads B once from
+// HBM: the lower triangle is cut into 256 x 256 tiles, one workgroup per
+// tile, one row per work-item, so every column access of a wavefront is a
+// contiguous 512-byte run.  Per-tile partial sums are reduced afterwards in
+// a fixed order (no floating-point atomics, bitwise reproducible).
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace bd {
+
+namespace {
+
+constexpr int kTv = 256;  // TRMV tile (rows = cols = threads)
+
+__device__ __forceinline__ void tri_index(int t, int& r, int& c) {
+  // t -> (r, c) with r >= c, t = r(r+1)/2 + c
+  int rr = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((rr + 1) * (rr + 2) / 2 <= t) ++rr;
+  while (rr * (rr + 1) / 2 > t) --rr;
+  r = rr;
+  c = t - rr * (rr + 1) / 2;
+}
+
+__global__ __launch_bounds__(256) void noise_kernel(double* __restrict__ xi, int64_t n,
+                                                     uint64_t seed, uint64_t chain,
+                                                     uint64_t step, int uniform) {
+  const int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk * 4 >= n) return;
+  double z[4];
+  noise4(seed, chain, step, (uint64_t)blk, uniform, z);
+#pragma unroll
+  for (int l = 0; l < 4; ++l)
+    if (blk * 4 + l < n) xi[blk * 4 + l] = z[l];
+}
+
+__global__ __launch_bounds__(kTv) void trmv_tile_kernel(const double* __restrict__ L, int64_t ld,
+                                                         int64_t n, const double* __restrict__ xi,
+                                                         double* __restrict__ part) {
+  __shared__ double xs[kTv];
+  int rt, ct;
+  tri_index(blockIdx.x, rt, ct);
+  const int64_t i = (int64_t)rt * kTv + threadIdx.x;
+  const int64_t j0 = (int64_t)ct * kTv;
+  {
+    const int64_t j = j0 + threadIdx.x;
+    xs[threadIdx.x] = (j < n) ? xi[j] : 0.0;
+  }
+  __syncthreads();
+  if (i >= n) return;
+  int jend = kTv;
+  if (j0 + jend > n) jend = (int)(n - j0);
+  if (rt == ct) jend = (int)(i - j0) + 1;  // diagonal tile: j <= i
+  const double* Lp = L + j0 * ld + i;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  int jj = 0;
+  for (; jj + 4 <= jend; jj += 4) {
+    acc0 += Lp[(int64_t)(jj + 0) * ld] * xs[jj + 0];
+    acc1 += Lp[(int64_t)(jj + 1) * ld] * xs[jj + 1];
+    acc2 += Lp[(int64_t)(jj + 2) * ld] * xs[jj + 2];
+    acc3 += Lp[(int64_t)(jj + 3) * ld] * xs[jj + 3];
+  }
+  for (; jj < jend; ++jj) acc0 += Lp[(int64_t)jj * ld] * xs[jj];
+  part[(int64_t)ct * n + i] = (acc0 + acc1) + (acc2 + acc3);
+}
+
+__global__ __launch_bounds__(256) void trmv_reduce_kernel(const double* __restrict__ part,
+                                                           int64_t n, double c,
+                                                           double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int rt = (int)(i / kTv);
+  double s = 0.0;
+  for (int ct = 0; ct <= rt; ++ct) s += part[(int64_t)ct * n + i];
+  y[i] = c * s;
+}
+
+__global__ __launch_bounds__(256) void predictor_kernel(const double* __restrict__ x,
+                                                         const double* __restrict__ y,
+                                                         double* __restrict__ xs, int N, double dt,
+                                                         double k0, double k1, double k2,
+                                                         double k3, double k4, double k5,
+                                                         double k6, double k7, double k8) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double r0 = x[3 * i], r1 = x[3 * i + 1], r2 = x[3 * i + 2];
+  // Eq. 5 flow term kappa . r_i, unweighted by D (Eq. 6)
+  const double v0 = k0 * r0 + k1 * r1 + k2 * r2;
+  const double v1 = k3 * r0 + k4 * r1 + k5 * r2;
+  const double v2 = k6 * r0 + k7 * r1 + k8 * r2;
+  xs[3 * i] = r0 + dt * v0 + y[3 * i];
+  xs[3 * i + 1] = r1 + dt * v1 + y[3 * i + 1];
+  xs[3 * i + 2] = r2 + dt * v2 + y[3 * i + 2];
+}
+
+}  // namespace
+
+static int64_t trmv_tiles(int64_t n) { return (n + kTv - 1) / kTv; }
+
+size_t brownian_workspace_bytes(int64_t n) {
+  const int64_t nt = trmv_tiles(n);
+  return align_up(sizeof(double) * n, 256) + align_up(sizeof(double) * nt * n, 256);
+}
+
+hipError_t launch_brownian(hipStream_t s, const bd_params_t& p, int64_t step, const double* L,
+                           int64_t ld, double* y, double* xi_out, void* ws) {
+  const int64_t n = 3 * (int64_t)p.n_beads;
+  double* xi = static_cast<double*>(ws);
+  double* part = reinterpret_cast<double*>(static_cast<char*>(ws) +
+                                           align_up(sizeof(double) * n, 256));
+  const int64_t nblk = (n + 3) / 4;
+  hipLaunchKernelGGL(noise_kernel, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, xi, n,
+                     p.seed, p.chain_id, (uint64_t)step, p.noise == BD_NOISE_UNIFORM_PAPER);
+  const int64_t nt = trmv_tiles(n);
+  const int64_t ntiles = nt * (nt + 1) / 2;
+  hipLaunchKernelGGL(trmv_tile_kernel, dim3((unsigned)ntiles), dim3(kTv), 0, s, L, ld, n, xi, part);
+  const double c = (p.noise == BD_NOISE_UNIFORM_PAPER) ? sqrt(6.0 * p.dt) : sqrt(2.0 * p.dt);
+  hipLaunchKernelGGL(trmv_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+                     n, c, y);
+  if (xi_out) {
+    hipError_t e = hipMemcpyAsync(xi_out, xi, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_predictor(hipStream_t s, const bd_params_t& p, const double* x, const double* y,
+                            double* xs) {
+  const int N = p.n_beads;
+  const double* k = p.kappa;
+  hipLaunchKernelGGL(predictor_kernel, dim3((N + 255) / 256), dim3(256), 0, s, x, y, xs, N, p.dt,
+                     k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], k[8]);
+  return hipGetLastError();
+}
+
+}  // namespace bd
