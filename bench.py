@@ -1,0 +1,288 @@
+#!/usr/bin/env python3
+"""Benchmark of the bead-rod BD + RPY hot path on one MI355X.
+
+Workload: one chain of N = 4096 beads (3N = 12288), b = 1, h* = 0.25,
+a = 0.5, uniaxial extension at Wi = 5, dt = 5e-5, seeded random-walk start
+(synthetic; the paper uses no dataset).  A step is one full pass of the hot
+path: RPY assembly, Cholesky, correlated noise, predictor and rod-tension
+solve.  Reports BD steps/s for the mixed-precision form (headline) and for
+FP64, the Cholesky TFLOP/s of both, the roofline of the dominant kernel and
+the CPU oracle on a bounded sample.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6   # TFLOP/s, MI355X dense FP64 (vector = matrix)
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X dense FP32 matrix
+PEAK_HBM = 8000.0  # GB/s
+METRIC = "BD steps/s + Cholesky TFLOP/s at 3N=12288, mixed vs FP64 on 1 MI355X"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def chol_flops(n: int) -> float:
+    return n**3 / 3.0 + n**2 / 2.0 + n / 6.0
+
+
+def syrk_flops_per_factor(n: int, nb: int) -> tuple[float, int]:
+    """Algorithmic flops of the lower trailing updates (2 per multiply-add
+    over the m(m+1)/2 lower elements, rank nb) and their launch count."""
+    tot, cnt = 0.0, 0
+    k = 0
+    while k < n:
+        w = min(nb, n - k)
+        m = n - k - w
+        if m > 0:
+            tot += m * (m + 1) * w
+            cnt += 1
+        k += nb
+    return tot, cnt
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--chol-reps", type=int, default=10)
+    ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--cpu-beads", type=int, default=2048,
+                    help="chain length of the CPU oracle sample (scaled to N=4096 by n^3)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=["all", "mixed", "fp64"], default="all",
+                    help="restrict the timed steps to one precision (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs one chain on one GPU; --gpus must be 1 "
+              "(independent chains shard across GPUs with no communication)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2208_06559_amd import binding as B
+    from paper_2208_06559_amd import inputs as I
+
+    w = I.LONG_UNIAXIAL
+    N, n = w.n_beads, w.n
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    kw = dict(dt=w.dt, kappa=w.kappa, seed=w.seed, hstar=w.hstar, a=w.a, b=w.b)
+    p = B.make_params(N, **kw)
+    x0_np = w.initial()
+    x0 = torch.tensor(x0_np, dtype=torch.float64, device=dev)
+    h = B.Handle(0)
+    precs = {"mixed": B.PREC_MIXED, "fp64": B.PREC_FP64}
+    if args.only != "all":
+        precs = {args.only: precs[args.only]}
+
+    # ---------------------------------------------------------- step rate
+    result = {}
+    finals = {}
+    for name, prec in precs.items():
+        ws = h.workspace(B.OP_STEP, n, prec)
+        x = x0.clone()
+        for s in range(args.warmup):
+            h.step(p, s, x, prec, ws)
+        info = h.info()
+        if info["status"] != B.OK:
+            raise RuntimeError(f"{name} warmup failed: {info}")
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        for s in range(args.steps):
+            h.step(p, args.warmup + s, x, prec, ws)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = ev0.elapsed_time(ev1)
+        info = h.info()
+        if info["status"] != B.OK:
+            raise RuntimeError(f"{name} timed steps failed: {info}")
+        xf = x.cpu().numpy()
+        rods = np.linalg.norm(np.diff(xf, axis=0), axis=1)
+        ms = 1e3 * wall / args.steps
+        result[name] = {
+            "steps_per_s": args.steps / wall,
+            "ms_per_step": ms,
+            "gpu_event_ms_per_step": gpu_ms / args.steps,
+            "newton_iters_last": info["newton_iters"],
+            "krylov_iters_last": info["krylov_iters"],
+            "max_rod_err_final": float(np.abs(rods - w.b).max()),
+        }
+        finals[name] = xf
+        log(f"{name}: {result[name]['steps_per_s']:.2f} steps/s ({ms:.3f} ms/step)")
+
+    # ------------------------------------------------ Cholesky TFLOP/s
+    ld = n
+    D = torch.empty((n, ld), dtype=torch.float64, device=dev)
+    for name, prec in precs.items():
+        ws = h.workspace(B.OP_CHOLESKY, n, prec)
+        times = []
+        for r in range(args.chol_reps):
+            h.rpy_assemble(p, x0, D, ld, B.FILL_LOWER)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            h.cholesky(D, n, ld, prec, ws)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        if h.info()["status"] != B.OK:
+            raise RuntimeError(f"{name} cholesky failed")
+        med = float(np.median(times))
+        tf = chol_flops(n) / (med * 1e-3) / 1e12
+        peak = PEAK_FP32 if prec == B.PREC_MIXED else PEAK_FP64
+        result[name].update({"cholesky_ms": med, "cholesky_tflops": tf,
+                             "cholesky_frac_of_peak": tf / peak, "peak_tflops": peak})
+        log(f"{name}: cholesky {med:.3f} ms = {tf:.2f} TFLOP/s ({100 * tf / peak:.1f}% of {peak})")
+
+    # ------------------------------------ residual and position error
+    extra = {}
+    Dfull = torch.empty((n, ld), dtype=torch.float64, device=dev)
+    h.rpy_assemble(p, x0, Dfull, ld, B.FILL_FULL)
+    Dm = B.matrix_view(Dfull, n)
+    dn = torch.linalg.norm(Dm).item()
+    for name, prec in precs.items():
+        A = Dfull.clone()
+        h.cholesky(A, n, ld, prec, h.workspace(B.OP_CHOLESKY, n, prec))
+        L = torch.tril(B.matrix_view(A, n))
+        res = torch.linalg.norm(L @ L.T - Dm).item() / dn
+        result[name]["residual_LLT_minus_D_over_D"] = res
+        del A, L
+        torch.cuda.empty_cache()
+    if len(precs) == 2:
+        xs = {}
+        for name, prec in precs.items():
+            xx = x0.clone()
+            h.step(p, 0, xx, prec, h.workspace(B.OP_STEP, n, prec))
+            xs[name] = xx.cpu().numpy()
+        extra["position_error_1step"] = float(np.abs(xs["mixed"] - xs["fp64"]).max() / w.b)
+        extra["position_error_after_run"] = float(
+            np.abs(finals["mixed"] - finals["fp64"]).max() / w.b)
+    del Dfull, Dm, D
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------- dominant-kernel roofline
+    head = "mixed" if "mixed" in precs else next(iter(precs))
+    hprec = precs[head]
+    x = x0.clone()
+    ws = h.workspace(B.OP_STEP, n, hprec)
+    h.step(p, 0, x, hprec, ws)
+    torch.cuda.synchronize()
+    h.profile_begin()
+    for s in range(args.profile_steps):
+        h.step(p, 1 + s, x, hprec, ws)
+    stats = h.profile_end()
+    tot_ms = sum(v[1] for v in stats.values())
+    kern = max(stats, key=lambda k: stats[k][1])
+    launches, kms = stats[kern]
+    breakdown = {k: {"launches_per_step": v[0] / args.profile_steps,
+                     "ms_per_step": v[1] / args.profile_steps,
+                     "share": v[1] / tot_ms} for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+    nb = 128
+    roof = None
+    if kern.startswith("syrk_update"):
+        fl, cnt = syrk_flops_per_factor(n, nb)
+        assert launches == cnt * args.profile_steps, (launches, cnt)
+        achieved = fl * args.profile_steps / (kms * 1e-3) / 1e12
+        peak = PEAK_FP32 if kern.endswith("f32") else PEAK_FP64
+        roof = {"bound": "mfma", "kernel": kern, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "algorithmic_flops_per_launch": fl / cnt, "avg_launch_ms": kms / launches,
+                "launches": launches}
+    else:
+        roof = {"bound": "unknown", "kernel": kern, "achieved": None, "peak": None,
+                "unit": None, "frac": None, "traffic": None}
+    log(f"dominant kernel {kern}: {roof}")
+
+    # ------------------------------------------------ library context
+    try:
+        Dt = torch.empty((n, n), dtype=torch.float64, device=dev)
+        Dbuf = torch.empty((n, ld), dtype=torch.float64, device=dev)
+        h.rpy_assemble(p, x0, Dbuf, ld, B.FILL_FULL)
+        Dt.copy_(B.matrix_view(Dbuf, n))
+        del Dbuf
+        torch.linalg.cholesky(Dt)
+        torch.cuda.synchronize()
+        tt = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            torch.linalg.cholesky(Dt)
+            e1.record()
+            torch.cuda.synchronize()
+            tt.append(e0.elapsed_time(e1))
+        lib_ms = float(np.median(tt))
+        extra["torch_linalg_cholesky_fp64"] = {"ms": lib_ms,
+                                               "tflops": chol_flops(n) / (lib_ms * 1e-3) / 1e12}
+        del Dt
+        torch.cuda.empty_cache()
+    except Exception as e:  # context only
+        extra["torch_linalg_cholesky_fp64"] = {"error": str(e)[:200]}
+
+    # ------------------------------------------------ CPU oracle sample
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as o
+        Ns = min(args.cpu_beads, N)
+        po = o.make_params(Ns, **kw)
+        xs0 = x0_np[:Ns].copy()
+        t0 = time.perf_counter()
+        _, io = o.step(po, 0, xs0)
+        dt_s = time.perf_counter() - t0
+        scale = (Ns / N) ** 3
+        cpu = {"value": scale / dt_s, "unit": "steps/s", "cores": o.num_threads(), "kind": "oracle",
+               "sample": f"1 oracle FP64 step of the same chain truncated to N={Ns} "
+                         f"(n={3 * Ns}), {dt_s:.2f} s measured, scaled by (n_s/n)^3 = "
+                         f"{scale:.4g} to n={n}",
+               "measured_s_per_step": dt_s, "status": io["status"]}
+        log(f"cpu oracle: {cpu}")
+
+    mixed = result.get("mixed")
+    fp64 = result.get("fp64")
+    headrec = result[head]
+    out = {
+        "metric": METRIC,
+        "value": headrec["steps_per_s"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": headrec["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-mfma+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_beads": N, "n": n, "b": w.b, "hstar": w.hstar,
+                   "a": w.a, "dt": w.dt, "flow": w.flow, "wi": w.wi, "rate": w.rate,
+                   "precision": head, "chains": 1},
+        "mixed": mixed,
+        "fp64": fp64,
+        "mixed_vs_fp64_steps": (mixed["steps_per_s"] / fp64["steps_per_s"]) if mixed and fp64 else None,
+        "roofline": roof,
+        "kernel_breakdown": breakdown,
+        "cpu_baseline": cpu,
+        "context": extra,
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

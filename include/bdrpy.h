@@ -160,6 +160,21 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
 /* Synchronise the handle's stream and return the info of the last call. */
 bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out);
 
+/* Per-kernel timing (instrumentation, not part of the method).  Between
+ * bd_profile_begin and bd_profile_end every kernel the handle launches is
+ * bracketed by HIP events on the handle's stream.  bd_profile_end
+ * synchronises, writes up to max_out entries (one per kernel name: launch
+ * count and summed duration), sets *n_out to the number of distinct kernels
+ * and switches timing off. */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} bd_kernel_stat_t;
+
+bd_status_t bd_profile_begin(bd_handle_t h);
+bd_status_t bd_profile_end(bd_handle_t h, bd_kernel_stat_t* out, int32_t max_out, int32_t* n_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,7 @@
 #include "bdo.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -620,3 +621,5 @@ int bdo_run_many(const bdo_params* p, int32_t nchains, const uint64_t* chain_ids
   }
   return worst;
 }
+
+int bdo_num_threads(void) { return omp_get_max_threads(); }

@@ -108,6 +108,9 @@ int bdo_run(const bdo_params* p, int64_t step0, int64_t nsteps, double* x_inout,
 int bdo_run_many(const bdo_params* p, int32_t nchains, const uint64_t* chain_ids,
                  int64_t step0, int64_t nsteps, double* x, int32_t* status_out);
 
+/* OpenMP threads the oracle's parallel loops use. */
+int bdo_num_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -102,6 +102,8 @@ def lib():
         L.bdo_run_many.argtypes = [pp, C.c_int32, u64p, C.c_int64, C.c_int64, dp,
                                    C.POINTER(C.c_int32)]
         L.bdo_run_many.restype = C.c_int
+        L.bdo_num_threads.argtypes = []
+        L.bdo_num_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -212,3 +214,7 @@ def run_many(p: Params, chain_ids, step0: int, nsteps: int, X: np.ndarray):
     lib().bdo_run_many(C.byref(p), len(ids), ids.ctypes.data_as(C.POINTER(C.c_uint64)), step0,
                        nsteps, _dp(XX), st.ctypes.data_as(C.POINTER(C.c_int32)))
     return XX, st
+
+
+def num_threads() -> int:
+    return int(lib().bdo_num_threads())

@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "BD_OK", 1: "BD_ERR_PARAM", 2: "BD_ERR_NOT_SPD", 3: "BD_ERR_N
                 4: "BD_ERR_HIP", 5: "BD_ERR_ALLOC", 6: "BD_ERR_UNSUPPORTED"}
 
 EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_rpy_assemble",
-           "bd_cholesky", "bd_brownian", "bd_constrain", "bd_step", "bd_get_info")
+           "bd_cholesky", "bd_brownian", "bd_constrain", "bd_step", "bd_get_info",
+           "bd_profile_begin", "bd_profile_end")
 
 
 class BdError(RuntimeError):
@@ -90,6 +91,11 @@ def make_params(n_beads: int, *, b=1.0, hstar=0.25, a=0.5, dt=1e-4, kappa=None, 
     return p
 
 
+class KernelStat(C.Structure):
+    """Mirror of bd_kernel_stat_t."""
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
 _lib = None
 
 
@@ -111,6 +117,8 @@ def lib():
         L.bd_constrain.argtypes = [vp, pp, dp, dp, dp, vp, C.c_size_t]
         L.bd_step.argtypes = [vp, pp, C.c_int64, dp, C.c_int, vp, C.c_size_t]
         L.bd_get_info.argtypes = [vp, C.POINTER(Info)]
+        L.bd_profile_begin.argtypes = [vp]
+        L.bd_profile_end.argtypes = [vp, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -224,6 +232,18 @@ class Handle:
         self._sync_stream()
         _check(lib().bd_step(self._h, C.byref(p), step, _dev_f64(x, "x", n), prec, ws.data_ptr(),
                              ws.numel() * ws.element_size()), "bd_step")
+
+    def profile_begin(self):
+        self._sync_stream()
+        _check(lib().bd_profile_begin(self._h), "bd_profile_begin")
+
+    def profile_end(self) -> dict:
+        """{kernel name: (launches, total_ms)} since profile_begin."""
+        buf = (KernelStat * 64)()
+        n = C.c_int32(0)
+        _check(lib().bd_profile_end(self._h, buf, 64, C.byref(n)), "bd_profile_end")
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
+                for i in range(min(n.value, 64))}
 
     def info(self) -> dict:
         out = Info()

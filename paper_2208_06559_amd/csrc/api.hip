@@ -7,16 +7,24 @@
 #include <new>
 
 #include "common.hpp"
+#include "profile.hpp"
 
 namespace bd {
 int constrain_max_beads();
-}
+Profiler* profiler_new();
+void profiler_delete(Profiler* p);
+int profiler_collect(Profiler* p, hipStream_t s, bd_kernel_stat_t* out, int max_out);
+}  // namespace bd
 
 struct bd_handle_s {
   int device;
   hipStream_t stream;
   bd::DevState* st;    // device
   bd::DevState* host;  // pinned host mirror
+  bd::Profiler* prof;  // per-kernel timing, or null
+  int prof_on;
+  hipStream_t aux;     // lookahead stream of the Cholesky (default priority)
+  hipEvent_t ev[3];    // fork / panel-ready / rest-done events
 };
 
 namespace {
@@ -87,19 +95,38 @@ __global__ void commit_positions_kernel(double* x, const double* xs, int64_t n,
 
 bd_status_t hip_status(hipError_t e) { return e == hipSuccess ? BD_OK : BD_ERR_HIP; }
 
+// Makes the handle's device current and its profiler (if on) active for the
+// calling thread until the end of the call.
+struct CallScope {
+  explicit CallScope(bd_handle_t h) { bd::g_prof = (h && h->prof_on) ? h->prof : nullptr; }
+  ~CallScope() { bd::g_prof = nullptr; }
+};
+
 bd_status_t enter(bd_handle_t h) {
   if (!h) return BD_ERR_PARAM;
   return hip_status(hipSetDevice(h->device));
 }
 
 hipError_t reset(bd_handle_t h) {
-  hipLaunchKernelGGL(reset_state_kernel, dim3(1), dim3(1), 0, h->stream, h->st);
+  BD_LAUNCH("reset_state", reset_state_kernel, dim3(1), dim3(1), 0, h->stream, h->st);
   return hipGetLastError();
 }
 
 }  // namespace
 
 extern "C" {
+
+// Releases whatever a (possibly partially built) handle holds.
+static void release(bd_handle_s* h) {
+  if (h->aux) (void)hipStreamSynchronize(h->aux);
+  for (int i = 0; i < 3; ++i)
+    if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
+  if (h->st) (void)hipFree(h->st);
+  if (h->host) (void)hipHostFree(h->host);
+  if (h->prof) bd::profiler_delete(h->prof);
+  delete h;
+}
 
 bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   if (!out) return BD_ERR_PARAM;
@@ -117,17 +144,22 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   h->stream = static_cast<hipStream_t>(hip_stream);
   h->st = nullptr;
   h->host = nullptr;
+  h->prof = nullptr;
+  h->prof_on = 0;
+  h->aux = nullptr;
+  h->ev[0] = h->ev[1] = h->ev[2] = nullptr;
   if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
       hipHostMalloc(&h->host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
-    if (h->st) (void)hipFree(h->st);
-    delete h;
+    release(h);
     return BD_ERR_ALLOC;
   }
+  bool ok = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i < 3 && ok; ++i)
+    ok = hipEventCreateWithFlags(&h->ev[i], hipEventDisableTiming) == hipSuccess;
   memset(h->host, 0, sizeof(DevState));
-  if (hipMemcpy(h->st, h->host, sizeof(DevState), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(h->st);
-    (void)hipHostFree(h->host);
-    delete h;
+  if (ok) ok = hipMemcpy(h->st, h->host, sizeof(DevState), hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    release(h);
     return BD_ERR_HIP;
   }
   *out = h;
@@ -138,9 +170,7 @@ bd_status_t bd_destroy(bd_handle_t h) {
   if (!h) return BD_ERR_PARAM;
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
-  (void)hipFree(h->st);
-  (void)hipHostFree(h->host);
-  delete h;
+  release(h);
   return BD_OK;
 }
 
@@ -174,6 +204,7 @@ bd_status_t bd_workspace_size(bd_op_t op, int64_t n, bd_precision_t prec, size_t
 
 bd_status_t bd_rpy_assemble(bd_handle_t h, const bd_params_t* p, const double* d_x, double* d_D,
                             int64_t ld, bd_fill_t fill) {
+  CallScope scope(h);
   bd_status_t e = enter(h);
   if (e != BD_OK) return e;
   if (!params_ok(p) || !d_x || !d_D) return BD_ERR_PARAM;
@@ -185,16 +216,18 @@ bd_status_t bd_rpy_assemble(bd_handle_t h, const bd_params_t* p, const double* d
 
 bd_status_t bd_cholesky(bd_handle_t h, int64_t n, double* d_A, int64_t ld, bd_precision_t prec,
                         void* d_ws, size_t ws_bytes) {
+  CallScope scope(h);
   bd_status_t e = enter(h);
   if (e != BD_OK) return e;
   if (n < 1 || !d_A || ld < n || !prec_ok(prec) || !d_ws) return BD_ERR_PARAM;
   if (ws_bytes < bd::cholesky_workspace_bytes(n, prec)) return BD_ERR_PARAM;
   if (reset(h) != hipSuccess) return BD_ERR_HIP;
-  return hip_status(bd::launch_cholesky(h->stream, n, d_A, ld, prec, d_ws, h->st));
+  return hip_status(bd::launch_cholesky(h->stream, h->aux, h->ev, n, d_A, ld, prec, d_ws, h->st));
 }
 
 bd_status_t bd_brownian(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_L,
                         int64_t ld, double* d_y, double* d_xi_out, void* d_ws, size_t ws_bytes) {
+  CallScope scope(h);
   bd_status_t e = enter(h);
   if (e != BD_OK) return e;
   if (!params_ok(p) || !d_L || !d_y || !d_ws) return BD_ERR_PARAM;
@@ -206,6 +239,7 @@ bd_status_t bd_brownian(bd_handle_t h, const bd_params_t* p, int64_t step, const
 
 bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_old,
                          double* d_x_pred_inout, double* d_T_out, void* d_ws, size_t ws_bytes) {
+  CallScope scope(h);
   bd_status_t e = enter(h);
   if (e != BD_OK) return e;
   if (!params_ok(p) || !d_x_old || !d_x_pred_inout || !d_ws) return BD_ERR_PARAM;
@@ -218,6 +252,7 @@ bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_
 
 bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d_x,
                     bd_precision_t prec, void* d_ws, size_t ws_bytes) {
+  CallScope scope(h);
   bd_status_t e = enter(h);
   if (e != BD_OK) return e;
   if (!params_ok(p) || !d_x || !d_ws || !prec_ok(prec)) return BD_ERR_PARAM;
@@ -233,14 +268,15 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
   hipStream_t s = h->stream;
   hipError_t he = reset(h);
   if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
-  if (he == hipSuccess) he = bd::launch_cholesky(s, n, D, ld, prec, base + L.chol, h->st);
+  if (he == hipSuccess)
+    he = bd::launch_cholesky(s, h->aux, h->ev, n, D, ld, prec, base + L.chol, h->st);
   if (he == hipSuccess)
     he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);
   if (he == hipSuccess)
     he = bd::launch_constrain(s, *p, d_x, xs, nullptr, base + L.cons, h->st, h->host);
   if (he == hipSuccess) {
-    hipLaunchKernelGGL(commit_positions_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+    BD_LAUNCH("commit_positions", commit_positions_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        s, d_x, xs, n, h->st);
     he = hipGetLastError();
   }
@@ -256,6 +292,25 @@ bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out) {
     return BD_ERR_HIP;
   if (hipStreamSynchronize(h->stream) != hipSuccess) return BD_ERR_HIP;
   memcpy(out, h->host, sizeof(bd_info_t));
+  return BD_OK;
+}
+
+bd_status_t bd_profile_begin(bd_handle_t h) {
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!h->prof) h->prof = bd::profiler_new();
+  if (!h->prof) return BD_ERR_ALLOC;
+  h->prof_on = 1;
+  return BD_OK;
+}
+
+bd_status_t bd_profile_end(bd_handle_t h, bd_kernel_stat_t* out, int32_t max_out, int32_t* n_out) {
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!h->prof || max_out < 0) return BD_ERR_PARAM;
+  const int n = bd::profiler_collect(h->prof, h->stream, out, max_out);
+  if (n_out) *n_out = n;
+  h->prof_on = 0;
   return BD_OK;
 }
 

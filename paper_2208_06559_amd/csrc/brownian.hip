@@ -8,6 +8,7 @@
 // contiguous 512-byte run.  Per-tile partial sums are reduced afterwards in
 // a fixed order (no floating-point atomics, bitwise reproducible).
 #include "common.hpp"
+#include "profile.hpp"
 #include "philox.hpp"
 
 namespace bd {
@@ -112,13 +113,13 @@ hipError_t launch_brownian(hipStream_t s, const bd_params_t& p, int64_t step, co
   double* part = reinterpret_cast<double*>(static_cast<char*>(ws) +
                                            align_up(sizeof(double) * n, 256));
   const int64_t nblk = (n + 3) / 4;
-  hipLaunchKernelGGL(noise_kernel, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, xi, n,
+  BD_LAUNCH("noise", noise_kernel, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, xi, n,
                      p.seed, p.chain_id, (uint64_t)step, p.noise == BD_NOISE_UNIFORM_PAPER);
   const int64_t nt = trmv_tiles(n);
   const int64_t ntiles = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL(trmv_tile_kernel, dim3((unsigned)ntiles), dim3(kTv), 0, s, L, ld, n, xi, part);
+  BD_LAUNCH("trmv_tile", trmv_tile_kernel, dim3((unsigned)ntiles), dim3(kTv), 0, s, L, ld, n, xi, part);
   const double c = (p.noise == BD_NOISE_UNIFORM_PAPER) ? sqrt(6.0 * p.dt) : sqrt(2.0 * p.dt);
-  hipLaunchKernelGGL(trmv_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+  BD_LAUNCH("trmv_reduce", trmv_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
                      n, c, y);
   if (xi_out) {
     hipError_t e = hipMemcpyAsync(xi_out, xi, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
@@ -131,7 +132,7 @@ hipError_t launch_predictor(hipStream_t s, const bd_params_t& p, const double* x
                             double* xs) {
   const int N = p.n_beads;
   const double* k = p.kappa;
-  hipLaunchKernelGGL(predictor_kernel, dim3((N + 255) / 256), dim3(256), 0, s, x, y, xs, N, p.dt,
+  BD_LAUNCH("predictor", predictor_kernel, dim3((N + 255) / 256), dim3(256), 0, s, x, y, xs, N, p.dt,
                      k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], k[8]);
   return hipGetLastError();
 }

@@ -20,6 +20,7 @@
 // each result register of a wavefront covers 16 consecutive rows of 4
 // columns: 128-byte runs in column-major memory.
 #include "common.hpp"
+#include "profile.hpp"
 
 namespace bd {
 
@@ -196,10 +197,15 @@ struct SyrkCfg<float> {
 
 constexpr int kPad = 4;
 
+// Tile sets of one trailing update: every lower tile, only the first tile
+// column (the next panel, updated ahead), or every lower tile but the first
+// column.
+enum { kTilesAll = 0, kTilesNext = 1, kTilesRest = 2 };
+
 template <typename T>
 __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C, int64_t ld,
                                                            const T* __restrict__ L, int64_t ldl,
-                                                           int64_t m) {
+                                                           int64_t m, int tiles) {
   constexpr int KC = SyrkCfg<T>::KC;
   typedef typename SyrkCfg<T>::acc_t acc_t;
   constexpr int NLD = KC * kTS / 256;  // elements per thread per operand per chunk
@@ -207,7 +213,16 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
   __shared__ T Bs[2][KC][kTS + kPad];  // column side
 
   int ti, tj;
-  tri_index(blockIdx.x, ti, tj);
+  if (tiles == kTilesNext) {
+    ti = blockIdx.x;
+    tj = 0;
+  } else {
+    tri_index(blockIdx.x, ti, tj);
+    if (tiles == kTilesRest) {
+      ++ti;
+      ++tj;
+    }
+  }
   const int64_t row0 = (int64_t)ti * kTS, col0 = (int64_t)tj * kTS;
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
@@ -284,35 +299,99 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
 
 size_t cholesky_workspace_bytes(int64_t n, bd_precision_t prec) {
   size_t b = align_up(sizeof(double) * NB * NB, 256);
-  if (prec == BD_PREC_MIXED) b += align_up(sizeof(float) * (size_t)n * NB, 256);
+  if (prec == BD_PREC_MIXED) b += 2 * align_up(sizeof(float) * (size_t)n * NB, 256);
   return b;
 }
 
-hipError_t launch_cholesky(hipStream_t s, int64_t n, double* A, int64_t ld, bd_precision_t prec,
-                           void* ws, DevState* st) {
-  double* W = static_cast<double*>(ws);
-  float* P32 = (prec == BD_PREC_MIXED)
-                   ? reinterpret_cast<float*>(static_cast<char*>(ws) +
-                                              align_up(sizeof(double) * NB * NB, 256))
-                   : nullptr;
-  for (int64_t k = 0; k < n; k += NB) {
-    const int nb = (int)((n - k < NB) ? (n - k) : NB);
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, A, ld, k, nb, W, st);
-    const int64_t m = n - k - nb;
-    if (m <= 0) break;
-    hipLaunchKernelGGL(panel_solve_kernel, dim3((unsigned)((m + kRB - 1) / kRB)), dim3(256), 0, s,
-                       A, ld, k, nb, m, W, P32, n);
-    const int64_t mt = (m + kTS - 1) / kTS;
-    const unsigned ntiles = (unsigned)(mt * (mt + 1) / 2);
-    double* C = A + (k + nb) * ld + (k + nb);
-    if (P32) {
-      hipLaunchKernelGGL(syrk_update_kernel<float>, dim3(ntiles), dim3(256), 0, s, C, ld,
-                         (const float*)P32, n, m);
-    } else {
-      hipLaunchKernelGGL(syrk_update_kernel<double>, dim3(ntiles), dim3(256), 0, s, C, ld,
-                         (const double*)(A + k * ld + k + nb), ld, m);
-    }
+namespace {
+
+struct CholCtx {
+  int64_t n, ld;
+  double* A;
+  double* W;
+  float* P32[2];  // FP32 copies of consecutive panels (MIXED), else null
+  DevState* st;
+};
+
+hipError_t factor_panel(const CholCtx& c, hipStream_t s, int64_t k) {
+  const int nb = (int)((c.n - k < NB) ? (c.n - k) : NB);
+  BD_LAUNCH("potrf_diag", potrf_diag_kernel, dim3(1), dim3(256), 0, s, c.A, c.ld, k, nb, c.W,
+            c.st);
+  const int64_t m = c.n - k - nb;
+  if (m > 0) {
+    float* P = c.P32[(k / NB) & 1];
+    BD_LAUNCH("panel_solve", panel_solve_kernel, dim3((unsigned)((m + kRB - 1) / kRB)), dim3(256),
+              0, s, c.A, c.ld, k, nb, m, c.W, P, c.n);
   }
+  return hipGetLastError();
+}
+
+hipError_t trailing(const CholCtx& c, hipStream_t s, int64_t k, int tiles) {
+  const int64_t m = c.n - k - NB;
+  const int64_t mt = (m + kTS - 1) / kTS;
+  unsigned nt = 0;
+  if (tiles == kTilesAll) nt = (unsigned)(mt * (mt + 1) / 2);
+  if (tiles == kTilesNext) nt = (unsigned)mt;
+  if (tiles == kTilesRest) nt = (unsigned)((mt - 1) * mt / 2);
+  if (nt == 0) return hipSuccess;
+  double* C = c.A + (k + NB) * c.ld + (k + NB);
+  const float* P = c.P32[(k / NB) & 1];
+  if (P) {
+    BD_LAUNCH("syrk_update_f32", syrk_update_kernel<float>, dim3(nt), dim3(256), 0, s, C, c.ld, P,
+              c.n, m, tiles);
+  } else {
+    BD_LAUNCH("syrk_update_f64", syrk_update_kernel<double>, dim3(nt), dim3(256), 0, s, C, c.ld,
+              (const double*)(c.A + k * c.ld + k + NB), c.ld, m, tiles);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Right-looking blocked factorisation with depth-1 lookahead: while the
+// main stream applies panel k to the trailing matrix (all but the next tile
+// column), the auxiliary stream updates the next tile column first, then
+// factors the next diagonal block and solves the next panel.  Events order
+// the two streams; with aux == nullptr everything runs on `s` in order.
+hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[3], int64_t n, double* A,
+                           int64_t ld, bd_precision_t prec, void* ws, DevState* st) {
+  CholCtx c;
+  c.n = n;
+  c.ld = ld;
+  c.A = A;
+  c.st = st;
+  c.W = static_cast<double*>(ws);
+  c.P32[0] = c.P32[1] = nullptr;
+  if (prec == BD_PREC_MIXED) {
+    char* p = static_cast<char*>(ws) + align_up(sizeof(double) * NB * NB, 256);
+    c.P32[0] = reinterpret_cast<float*>(p);
+    c.P32[1] = reinterpret_cast<float*>(p + align_up(sizeof(float) * (size_t)n * NB, 256));
+  }
+  hipError_t e;
+  if (!aux) {
+    for (int64_t k = 0; k < n; k += NB) {
+      if ((e = factor_panel(c, s, k)) != hipSuccess) return e;
+      if (k + NB < n && (e = trailing(c, s, k, kTilesAll)) != hipSuccess) return e;
+    }
+    return hipGetLastError();
+  }
+  hipEvent_t ev_fork = ev[0], ev_panel = ev[1], ev_rest = ev[2];
+  if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
+  if ((e = factor_panel(c, aux, 0)) != hipSuccess) return e;
+  if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
+  for (int64_t k = 0; k + NB < n; k += NB) {
+    // main: panel k must be solved before it is applied
+    if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
+    // aux: the next tile column must have every earlier update
+    if (k > 0 && (e = hipStreamWaitEvent(aux, ev_rest, 0)) != hipSuccess) return e;
+    if ((e = trailing(c, aux, k, kTilesNext)) != hipSuccess) return e;
+    if ((e = factor_panel(c, aux, k + NB)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
+    if ((e = trailing(c, s, k, kTilesRest)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev_rest, s)) != hipSuccess) return e;
+  }
+  if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@
 //               tridiagonal solve in LDS), then writes the next f.
 // Once the iteration has finished both kernels return immediately.
 #include "common.hpp"
+#include "profile.hpp"
 #include "rpy_device.hpp"
 
 namespace bd {
@@ -520,18 +521,18 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
   const int ithreads = M > 0 ? M : 1;
   int iblk = (ithreads + 255) / 256;
   if (iblk < 16) iblk = 16;
-  hipLaunchKernelGGL(constrain_init_kernel, dim3(iblk), dim3(256), 0, s, x_old, xs, b, N, JC,
+  BD_LAUNCH("constrain_init", constrain_init_kernel, dim3(iblk), dim3(256), 0, s, x_old, xs, b, N, JC,
                      p.hstar, p.a, st);
-  hipLaunchKernelGGL(newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b, xs, T_out, N,
+  BD_LAUNCH("newton_controller", newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b, xs, T_out, N,
                      JC, p.dt, p.b, p.newton_tol, p.newton_maxit, st);
   const dim3 mvgrid((N + kMvI - 1) / kMvI, JC);
   const int cap = (p.newton_maxit + 1) * (kKmax + 2);
   constexpr int kPoll = 8;
   for (int done = 0; done < cap; done += kPoll) {
     for (int c = 0; c < kPoll; ++c) {
-      hipLaunchKernelGGL(dmatvec_kernel, mvgrid, dim3(256), 0, s, x_old, b.f, b.part, N, chunk,
+      BD_LAUNCH("dmatvec", dmatvec_kernel, mvgrid, dim3(256), 0, s, x_old, b.f, b.part, N, chunk,
                          p.hstar, p.a, st);
-      hipLaunchKernelGGL(newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b, xs, T_out,
+      BD_LAUNCH("newton_controller", newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b, xs, T_out,
                          N, JC, p.dt, p.b, p.newton_tol, p.newton_maxit, st);
     }
     hipError_t e = hipMemcpyAsync(&host_state->done, &st->done, sizeof(int32_t),

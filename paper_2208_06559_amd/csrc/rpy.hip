@@ -7,6 +7,7 @@
 // blocks with i >= j are touched and the diagonal block keeps its lower
 // part only.
 #include "common.hpp"
+#include "profile.hpp"
 #include "rpy_device.hpp"
 
 namespace bd {
@@ -60,7 +61,7 @@ hipError_t launch_rpy_assemble(hipStream_t s, const bd_params_t& p, const double
                                int64_t ld, int fill) {
   const int N = p.n_beads;
   dim3 grid((N + kRpyThreads - 1) / kRpyThreads, N);
-  hipLaunchKernelGGL(rpy_assemble_kernel, grid, dim3(kRpyThreads), 0, s, x, D, ld, N, p.hstar,
+  BD_LAUNCH("rpy_assemble", rpy_assemble_kernel, grid, dim3(kRpyThreads), 0, s, x, D, ld, N, p.hstar,
                      p.a, fill == BD_FILL_FULL ? 1 : 0);
   return hipGetLastError();
 }
