@@ -39,7 +39,9 @@ def chol_flops(n: int) -> float:
 
 def syrk_flops_per_factor(n: int, nb: int) -> tuple[float, int]:
     """Algorithmic flops of the lower trailing updates (2 per multiply-add
-    over the m(m+1)/2 lower elements, rank nb) and their launch count."""
+    over the m(m+1)/2 lower elements, rank nb) and their launch count: with
+    lookahead each panel's update is two launches, the next tile column and
+    (when there is more than one tile column) the rest."""
     tot, cnt = 0.0, 0
     k = 0
     while k < n:
@@ -47,7 +49,7 @@ def syrk_flops_per_factor(n: int, nb: int) -> tuple[float, int]:
         m = n - k - w
         if m > 0:
             tot += m * (m + 1) * w
-            cnt += 1
+            cnt += 1 + (1 if m > nb else 0)
         k += nb
     return tot, cnt
 
@@ -59,7 +61,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--chol-reps", type=int, default=10)
     ap.add_argument("--profile-steps", type=int, default=5)
-    ap.add_argument("--cpu-beads", type=int, default=2048,
+    ap.add_argument("--cpu-beads", type=int, default=4096,
                     help="chain length of the CPU oracle sample (scaled to N=4096 by n^3)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["all", "mixed", "fp64"], default="all",
@@ -177,37 +179,47 @@ def main() -> int:
     torch.cuda.empty_cache()
 
     # ------------------------------------------- dominant-kernel roofline
-    head = "mixed" if "mixed" in precs else next(iter(precs))
-    hprec = precs[head]
-    x = x0.clone()
-    ws = h.workspace(B.OP_STEP, n, hprec)
-    h.step(p, 0, x, hprec, ws)
-    torch.cuda.synchronize()
-    h.profile_begin()
-    for s in range(args.profile_steps):
-        h.step(p, 1 + s, x, hprec, ws)
-    stats = h.profile_end()
-    tot_ms = sum(v[1] for v in stats.values())
-    kern = max(stats, key=lambda k: stats[k][1])
-    launches, kms = stats[kern]
-    breakdown = {k: {"launches_per_step": v[0] / args.profile_steps,
-                     "ms_per_step": v[1] / args.profile_steps,
-                     "share": v[1] / tot_ms} for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
     nb = 128
-    roof = None
-    if kern.startswith("syrk_update"):
-        fl, cnt = syrk_flops_per_factor(n, nb)
-        assert launches == cnt * args.profile_steps, (launches, cnt)
-        achieved = fl * args.profile_steps / (kms * 1e-3) / 1e12
-        peak = PEAK_FP32 if kern.endswith("f32") else PEAK_FP64
-        roof = {"bound": "mfma", "kernel": kern, "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                "algorithmic_flops_per_launch": fl / cnt, "avg_launch_ms": kms / launches,
-                "launches": launches}
-    else:
-        roof = {"bound": "unknown", "kernel": kern, "achieved": None, "peak": None,
-                "unit": None, "frac": None, "traffic": None}
-    log(f"dominant kernel {kern}: {roof}")
+
+    def profile(prec_name):
+        pr = precs[prec_name]
+        xx = x0.clone()
+        wsp = h.workspace(B.OP_STEP, n, pr)
+        h.step(p, 0, xx, pr, wsp)
+        torch.cuda.synchronize()
+        h.profile_begin()
+        for s in range(args.profile_steps):
+            h.step(p, 1 + s, xx, pr, wsp)
+        stats = h.profile_end()
+        tot = sum(v[1] for v in stats.values())
+        kern = max(stats, key=lambda k: stats[k][1])
+        launches, kms = stats[kern]
+        brk = {k: {"launches_per_step": v[0] / args.profile_steps,
+                   "ms_per_step": v[1] / args.profile_steps,
+                   "share": v[1] / tot}
+               for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+        if kern.startswith("syrk_update"):
+            fl, cnt = syrk_flops_per_factor(n, nb)
+            assert launches == cnt * args.profile_steps, (launches, cnt)
+            achieved = fl * args.profile_steps / (kms * 1e-3) / 1e12
+            peak = PEAK_FP32 if kern.endswith("f32") else PEAK_FP64
+            rf = {"bound": "mfma", "kernel": kern, "achieved": achieved, "peak": peak,
+                  "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                  "algorithmic_flops_per_launch": fl / cnt, "avg_launch_ms": kms / launches,
+                  "launches": launches}
+        else:
+            rf = {"bound": "latency", "kernel": kern, "achieved": None, "peak": None,
+                  "unit": None, "frac": None, "traffic": None,
+                  "avg_launch_ms": kms / launches, "launches": launches}
+        log(f"{prec_name}: dominant kernel {kern}: {rf}")
+        return rf, brk
+
+    head = "mixed" if "mixed" in precs else next(iter(precs))
+    roof, breakdown = profile(head)
+    other = {}
+    for name in precs:
+        if name != head:
+            other[name] = dict(zip(("roofline", "kernel_breakdown"), profile(name)))
 
     # ------------------------------------------------ library context
     try:
@@ -276,6 +288,7 @@ def main() -> int:
         "mixed_vs_fp64_steps": (mixed["steps_per_s"] / fp64["steps_per_s"]) if mixed and fp64 else None,
         "roofline": roof,
         "kernel_breakdown": breakdown,
+        "other_precision_profile": other,
         "cpu_baseline": cpu,
         "context": extra,
     }

@@ -2,6 +2,7 @@
 // per-step orchestration (assemble -> Cholesky -> noise -> predictor ->
 // constraint), all on the handle's stream.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -23,6 +24,7 @@ struct bd_handle_s {
   bd::DevState* host;  // pinned host mirror
   bd::Profiler* prof;  // per-kernel timing, or null
   int prof_on;
+  int pairs_hint;      // D products the last tension solve needed
   hipStream_t aux;     // lookahead stream of the Cholesky (default priority)
   hipEvent_t ev[3];    // fork / panel-ready / rest-done events
 };
@@ -146,6 +148,7 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   h->host = nullptr;
   h->prof = nullptr;
   h->prof_on = 0;
+  h->pairs_hint = 0;
   h->aux = nullptr;
   h->ev[0] = h->ev[1] = h->ev[2] = nullptr;
   if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
@@ -153,8 +156,12 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
     release(h);
     return BD_ERR_ALLOC;
   }
-  bool ok = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess;
-  for (int i = 0; i < 3 && ok; ++i)
+  // BDRPY_LOOKAHEAD=0 runs the factorisation on the caller's stream only
+  // (for comparisons); by default the lookahead stream is used.
+  const char* la = getenv("BDRPY_LOOKAHEAD");
+  const bool lookahead = !(la && la[0] == '0');
+  bool ok = !lookahead || hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i < 3 && ok && lookahead; ++i)
     ok = hipEventCreateWithFlags(&h->ev[i], hipEventDisableTiming) == hipSuccess;
   memset(h->host, 0, sizeof(DevState));
   if (ok) ok = hipMemcpy(h->st, h->host, sizeof(DevState), hipMemcpyHostToDevice) == hipSuccess;
@@ -247,7 +254,7 @@ bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_
   if (ws_bytes < bd::constrain_workspace_bytes(p->n_beads)) return BD_ERR_PARAM;
   if (reset(h) != hipSuccess) return BD_ERR_HIP;
   return hip_status(bd::launch_constrain(h->stream, *p, d_x_old, d_x_pred_inout, d_T_out, d_ws,
-                                         h->st, h->host));
+                                         h->st, h->host, &h->pairs_hint));
 }
 
 bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d_x,
@@ -274,7 +281,8 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
     he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);
   if (he == hipSuccess)
-    he = bd::launch_constrain(s, *p, d_x, xs, nullptr, base + L.cons, h->st, h->host);
+    he = bd::launch_constrain(s, *p, d_x, xs, nullptr, base + L.cons, h->st, h->host,
+                               &h->pairs_hint);
   if (he == hipSuccess) {
     BD_LAUNCH("commit_positions", commit_positions_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        s, d_x, xs, n, h->st);

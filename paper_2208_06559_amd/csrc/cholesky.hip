@@ -3,9 +3,11 @@
 //
 // For each panel of width NB starting at column k:
 //   1. potrf_diag   one workgroup factors the NB x NB diagonal block in LDS
-//                   (FP64) and writes its triangular inverse W = L11^-1;
-//   2. panel_solve  L21 = A21 L11^-T = A21 W^T, an MFMA GEMM over row blocks
-//                   (FP64); in MIXED mode it also stores an FP32 copy of L21;
+//                   (FP64) and writes the inverses of its four 32 x 32
+//                   diagonal sub-blocks;
+//   2. panel_solve  L21 = A21 L11^-T by blocked forward substitution with
+//                   MFMA over row blocks (FP64); in MIXED mode it also stores
+//                   an FP32 copy of L21;
 //   3. syrk_update  A22 -= L21 L21^T on the lower tiles of the trailing
 //                   matrix with MFMA: FP64 operands/accumulators, or (MIXED)
 //                   FP32 operands with FP32 accumulation, subtracted into the
@@ -30,7 +32,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int NB = kNB;       // panel width
-constexpr int LDP = NB + 1;   // LDS leading dimension of the diagonal block
 constexpr int kTS = kTile;    // trailing-update tile
 
 __device__ __forceinline__ void tri_index(int t, int& r, int& c) {
@@ -39,6 +40,12 @@ __device__ __forceinline__ void tri_index(int t, int& r, int& c) {
   while (rr * (rr + 1) / 2 > t) --rr;
   r = rr;
   c = t - rr * (rr + 1) / 2;
+}
+
+__host__ __device__ __forceinline__ int xcd_contiguous(int t, int nwg) {
+  const int base = nwg / 8, rem = nwg % 8;
+  const int x = t % 8, q = t / 8;
+  return x * base + (x < rem ? x : rem) + q;
 }
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
@@ -52,127 +59,243 @@ __device__ __forceinline__ int res_row(d4, int lk, int r) { return lk + 4 * r; }
 __device__ __forceinline__ int res_row(f4, int lk, int r) { return 4 * lk + r; }
 
 // ------------------------------------------------------------------------
-// 1. Diagonal block: unblocked right-looking Cholesky in LDS, then the
-//    in-place inverse of the lower triangle (column j from the last to the
-//    first: W_jj = 1/L_jj, W_ij = -W_jj * sum_{j<k<=i} W_ik L_kj).
-//    Rows and columns beyond nb are padded with the identity.
+// 1. Diagonal block (NB x NB, FP64, one workgroup of 256 threads).
+//    Right-looking unblocked factorisation with the matrix in registers:
+//    thread (tr, tc) = (t % 16, t / 16) owns the interleaved 8 x 8 tile of
+//    rows tr + 16a and columns tc + 16b, so the shrinking trailing triangle
+//    stays spread over all threads.  Per column j the owners of column j
+//    scale it by 1/sqrt(pivot) and publish it through a 1 KB LDS buffer;
+//    every thread then applies the rank-1 update to its tile.  Afterwards
+//    four waves invert the four 32 x 32 diagonal blocks of L11 in parallel
+//    (forward substitution on the identity) for the panel solve.
+//    Writes L11 over A11 and the inverses Winv_p (32 x 32, column-major) to
+//    W.  Rows and columns beyond nb are padded with the identity.
 // ------------------------------------------------------------------------
+constexpr int SB = 32;          // diagonal sub-block of the panel solve
+constexpr int NSB = NB / SB;    // sub-blocks per diagonal block
+constexpr int SBB = SB * SB;    // doubles per 32 x 32 block
+constexpr int TT = NB / 16;     // tile rows/columns per thread (8)
+
+// 1/sqrt(d) to full FP64 accuracy: hardware estimate plus two Newton steps.
+__device__ __forceinline__ double rsqrt_refined(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double h = 0.5 * d * y;
+    y = fma(-h, y, 1.5) * y;
+  }
+  return y;
+}
+
+// Columns 16 JB .. 16 JB + 15 of the register-tiled factorisation (JB is a
+// template parameter so that every register index is a compile-time
+// constant).
+template <int JB>
+__device__ __forceinline__ void chol_block(double (&a)[TT][TT], double* __restrict__ col,
+                                           double* __restrict__ piv, int tr, int tc, int tid,
+                                           int64_t k, DevState* __restrict__ st) {
+  for (int jr = 0; jr < 16; ++jr) {
+    const int j = 16 * JB + jr;
+    __syncthreads();  // pivot published; previous column no longer read
+    if (tc == jr) {
+      const double d = *piv;
+      if (tid == jr * 16 + jr && !(d > 0.0) && st->potrf_info == 0) {
+        st->potrf_info = k + j + 1;
+        st->status = BD_ERR_NOT_SPD;
+      }
+      const double rs = rsqrt_refined(d);  // NaN for a non-positive pivot
+#pragma unroll
+      for (int ia = JB; ia < TT; ++ia) {
+        const int i = tr + 16 * ia;
+        if (i == j) {
+          a[ia][JB] = d * rs;
+          col[i] = a[ia][JB];
+        } else if (i > j) {
+          a[ia][JB] *= rs;
+          col[i] = a[ia][JB];
+        }
+      }
+    }
+    __syncthreads();  // column j of L published
+    // Only tiles ib >= JB, ia >= ib can hold live elements: for ia < ib every
+    // row is above every column; for ia > ib every row is below; within
+    // ia == ib only tr >= tc; and columns c > j need checking only at ib == JB.
+    double ci[TT], cc[TT];
+#pragma unroll
+    for (int ia = JB; ia < TT; ++ia) ci[ia] = col[tr + 16 * ia];
+#pragma unroll
+    for (int ib = JB; ib < TT; ++ib) cc[ib] = col[tc + 16 * ib];
+    const bool lower_diag = tr >= tc;
+    const bool col_live = tc > jr;  // column tc + 16 JB is past j
+#pragma unroll
+    for (int ib = JB; ib < TT; ++ib)
+#pragma unroll
+      for (int ia = ib; ia < TT; ++ia) {
+        bool live = true;
+        if (ia == ib) live = lower_diag;
+        if (ib == JB) live = live && col_live;
+        const double upd = fma(-ci[ia], cc[ib], a[ia][ib]);
+        a[ia][ib] = live ? upd : a[ia][ib];
+      }
+    // publish the next pivot (its owner has just updated it)
+    const int jn = j + 1;
+    if (tr == (jn & 15) && tc == (jn & 15)) {
+      if (jr < 15) {
+        *piv = a[JB][JB];
+      } else if (JB + 1 < TT) {
+        *piv = a[JB + 1 < TT ? JB + 1 : JB][JB + 1 < TT ? JB + 1 : JB];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A, int64_t ld,
                                                           int64_t k, int nb,
                                                           double* __restrict__ W,
                                                           DevState* __restrict__ st) {
-  __shared__ double S[NB * LDP];
+  __shared__ double col[NB];          // the current column of L
+  __shared__ double piv;              // the current pivot
+  __shared__ double Ld[NSB][SBB];     // diagonal 32 x 32 blocks of L, column-major
+  __shared__ double rowb[4][SB];      // per-wave row broadcast of the inversions
   const int tid = threadIdx.x;
+  const int tr = tid & 15, tc = tid >> 4;
   double* Akk = A + k * ld + k;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int c = idx / NB, r = idx % NB;
-    double v = 0.0;
-    if (c < nb && r < nb) {
-      if (r >= c) v = Akk[(int64_t)c * ld + r];
-    } else if (r == c) {
-      v = 1.0;
+  double a[TT][TT];
+#pragma unroll
+  for (int ia = 0; ia < TT; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < TT; ++ib) {
+      const int i = tr + 16 * ia, c = tc + 16 * ib;
+      double v = 0.0;
+      if (i < nb && c < nb) {
+        if (i >= c) v = Akk[(int64_t)c * ld + i];
+      } else if (i == c) {
+        v = 1.0;
+      }
+      a[ia][ib] = v;
     }
-    S[c * LDP + r] = v;
-  }
+  if (tid == 0) piv = a[0][0];
+  static_assert(TT == 8, "diagonal block tiling");
+  chol_block<0>(a, col, &piv, tr, tc, tid, k, st);
+  chol_block<1>(a, col, &piv, tr, tc, tid, k, st);
+  chol_block<2>(a, col, &piv, tr, tc, tid, k, st);
+  chol_block<3>(a, col, &piv, tr, tc, tid, k, st);
+  chol_block<4>(a, col, &piv, tr, tc, tid, k, st);
+  chol_block<5>(a, col, &piv, tr, tc, tid, k, st);
+  chol_block<6>(a, col, &piv, tr, tc, tid, k, st);
+  chol_block<7>(a, col, &piv, tr, tc, tid, k, st);
+  // L11 to global (lower part) and the diagonal blocks to LDS
+#pragma unroll
+  for (int ia = 0; ia < TT; ++ia)
+#pragma unroll
+    for (int ib = 0; ib < TT; ++ib) {
+      const int i = tr + 16 * ia, c = tc + 16 * ib;
+      if (i < nb && c < nb && i >= c) Akk[(int64_t)c * ld + i] = a[ia][ib];
+      if ((i >> 5) == (c >> 5)) Ld[i >> 5][(c & 31) * SB + (i & 31)] = (i >= c) ? a[ia][ib] : 0.0;
+    }
   __syncthreads();
-
-  for (int j = 0; j < nb; ++j) {
-    const double d = S[j * LDP + j];
-    const double dj = sqrt(d);  // NaN for a non-positive pivot
-    if (tid == 0 && !(d > 0.0) && st->potrf_info == 0) {
-      st->potrf_info = k + j + 1;
-      st->status = BD_ERR_NOT_SPD;
+  // wave p inverts diagonal block p: lane (r, h) keeps W[r][16h .. 16h+15]
+  {
+    const int p = tid >> 6, lane = tid & 63, r = lane & 31, h = lane >> 5;
+    const double* L = Ld[p];
+    double w[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) w[c] = (r == 16 * h + c) ? 1.0 : 0.0;
+    for (int q = 0; q < SB; ++q) {
+      const double lqq = L[q * SB + q];
+      if (r == q) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          w[c] = w[c] / lqq;
+          rowb[p][16 * h + c] = w[c];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (r > q) {
+        const double lrq = L[q * SB + r];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) w[c] = fma(-lrq, rowb[p][16 * h + c], w[c]);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
-    for (int i = j + 1 + tid; i < nb; i += 256) S[j * LDP + i] = S[j * LDP + i] / dj;
-    __syncthreads();
-    if (tid == 0) S[j * LDP + j] = dj;
-    const int g = tid >> 6, l = tid & 63;
-    for (int c = j + 1 + g; c < nb; c += 4) {
-      const double ljc = S[j * LDP + c];
-      for (int i = c + l; i < nb; i += 64) S[c * LDP + i] -= S[j * LDP + i] * ljc;
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < nb * nb; idx += 256) {
-    const int c = idx / nb, r = idx % nb;
-    if (r >= c) Akk[(int64_t)c * ld + r] = S[c * LDP + r];
-  }
-  __syncthreads();
-
-  // in-place inverse of the lower triangle
-  for (int j = nb - 1; j >= 0; --j) {
-    const double wjj = 1.0 / S[j * LDP + j];
-    double x = 0.0;
-    const int i = j + 1 + tid;
-    if (tid < 128 && i < nb) {
-      for (int kk = j + 1; kk <= i; ++kk) x += S[kk * LDP + i] * S[j * LDP + kk];
-    }
-    __syncthreads();
-    if (tid < 128 && i < nb) S[j * LDP + i] = -wjj * x;
-    if (tid == 0) S[j * LDP + j] = wjj;
-    __syncthreads();
-  }
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int c = idx / NB, r = idx % NB;
-    W[idx] = (r >= c) ? S[c * LDP + r] : 0.0;
+    double* Wp = W + p * SBB;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) Wp[(16 * h + c) * SB + r] = w[c];
   }
 }
 
 // ------------------------------------------------------------------------
-// 2. Panel solve X = A21 W^T for a block of 64 rows (all NB columns).
-//    The 64 x NB row block is staged in LDS, so the result can overwrite
-//    A21 in place.  Wave w computes output columns [32w, 32w+32); W is
-//    lower-triangular, so its K loop stops at column 32w+31.
+// 2. Panel solve X L11^T = A21 for a block of 32 rows, by blocked forward
+//    substitution over the four 32-column sub-panels:
+//      X(:,p) = (A(:,p) - sum_{q<p} X(:,q) L11(p,q)^T) Winv_p^T.
+//    Two waves, 16 rows each; the row block lives in LDS, so the result can
+//    overwrite A21 in place.  In MIXED mode an FP32 copy is stored as well.
 // ------------------------------------------------------------------------
-constexpr int kRB = 64;  // rows per panel-solve workgroup
+constexpr int kRB = 32;          // rows per panel-solve workgroup
+constexpr int kPsThreads = 128;  // two waves
 
-__global__ __launch_bounds__(256) void panel_solve_kernel(double* __restrict__ A, int64_t ld,
-                                                           int64_t k, int nb, int64_t m,
-                                                           const double* __restrict__ W,
-                                                           float* __restrict__ P32,
-                                                           int64_t ldp) {
-  __shared__ double As[NB][kRB + 1];
+__global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
+    double* __restrict__ A, int64_t ld, int64_t k, int nb, int64_t m, const double* __restrict__ W,
+    float* __restrict__ P32, int64_t ldp) {
+  __shared__ double Xs[NB][kRB + 4];  // Xs[col][row]
+  __shared__ double Ls[SB][NB + 4];   // Ls[c][q] = L11[32p + c][q], q < 32p
+  __shared__ double Ws[SB][SB + 4];   // Ws[c][r] = Winv_p[r][c]
   const int tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * kRB;
   double* A21 = A + k * ld + k + nb;
-  for (int idx = tid; idx < NB * kRB; idx += 256) {
+  const double* L11 = A + k * ld + k;
+  for (int idx = tid; idx < NB * kRB; idx += kPsThreads) {
     const int kk = idx / kRB, r = idx % kRB;
     const int64_t row = r0 + r;
-    As[kk][r] = (kk < nb && row < m) ? A21[(int64_t)kk * ld + row] : 0.0;
+    Xs[kk][r] = (kk < nb && row < m) ? A21[(int64_t)kk * ld + row] : 0.0;
+  }
+  const int i0 = 16 * w;
+  for (int p = 0; p < NSB; ++p) {
+    const int c0 = SB * p;
+    __syncthreads();  // previous sub-panel done with Ls/Ws
+    for (int idx = tid; idx < SB * c0; idx += kPsThreads) {
+      const int q = idx / SB, c = idx % SB;
+      Ls[c][q] = (c0 + c < nb && q < nb) ? L11[(int64_t)q * ld + c0 + c] : 0.0;
+    }
+    for (int idx = tid; idx < SBB; idx += kPsThreads) Ws[idx / SB][idx % SB] = W[p * SBB + idx];
+    __syncthreads();
+    // T = A(:,p) - X(:,0:c0) L11(p, 0:c0)^T
+    d4 acc[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
+    for (int kk = 0; kk < c0; kk += 4) {
+      const double b = Xs[kk + lk][i0 + lr];
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) acc[jt] = mfma(Ls[16 * jt + lr][kk + lk], b, acc[jt]);
+    }
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Xs[c0 + 16 * jt + res_row(acc[jt], lk, q)][i0 + lr] -= acc[jt][q];
+    // X(:,p) = T Winv_p^T (rows of this wave only, in place)
+    d4 x[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
+#pragma unroll
+    for (int kk = 0; kk < SB; kk += 4) {
+      const double b = Xs[c0 + kk + lk][i0 + lr];
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) x[jt] = mfma(Ws[kk + lk][16 * jt + lr], b, x[jt]);
+    }
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Xs[c0 + 16 * jt + res_row(x[jt], lk, q)][i0 + lr] = x[jt][q];
   }
   __syncthreads();
-  const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-  d4 acc[2][4];
-#pragma unroll
-  for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi) acc[bj][bi] = d4{0.0, 0.0, 0.0, 0.0};
-  const int kend = 32 * w + 32;
-  for (int k0 = 0; k0 < kend; k0 += 4) {
-    double af[2], bf[4];
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) af[bj] = W[(k0 + lk) * NB + 32 * w + 16 * bj + lr];
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi) bf[bi] = As[k0 + lk][16 * bi + lr];
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int bi = 0; bi < 4; ++bi) acc[bj][bi] = mfma(af[bj], bf[bi], acc[bj][bi]);
+  for (int idx = tid; idx < NB * kRB; idx += kPsThreads) {
+    const int kk = idx / kRB, r = idx % kRB;
+    const int64_t row = r0 + r;
+    if (kk < nb && row < m) {
+      const double v = Xs[kk][r];
+      A21[(int64_t)kk * ld + row] = v;
+      if (P32) P32[(int64_t)kk * ldp + row] = (float)v;
+    }
   }
-#pragma unroll
-  for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + 16 * bi + lr;
-        const int col = 32 * w + 16 * bj + res_row(acc[bj][bi], lk, r);
-        if (row < m && col < nb) {
-          const double v = acc[bj][bi][r];
-          A21[(int64_t)col * ld + row] = v;
-          if (P32) P32[(int64_t)col * ldp + row] = (float)v;
-        }
-      }
 }
 
 // ------------------------------------------------------------------------
@@ -202,6 +325,10 @@ constexpr int kPad = 4;
 // column.
 enum { kTilesAll = 0, kTilesNext = 1, kTilesRest = 2 };
 
+// Pipeline: the C tile is loaded into registers before the K loop (its
+// latency hides behind the MFMA work), operand chunks of KC columns go
+// global -> registers two chunks ahead and registers -> LDS one chunk
+// ahead (LDS double buffer).
 template <typename T>
 __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C, int64_t ld,
                                                            const T* __restrict__ L, int64_t ldl,
@@ -212,12 +339,15 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
   __shared__ T As[2][KC][kTS + kPad];  // row side
   __shared__ T Bs[2][KC][kTS + kPad];  // column side
 
+  // XCD x receives workgroups x, x+8, ...: cnt(x) = base + (x < rem) of them;
+  // the q-th of them takes tile x*base + min(x, rem) + q (a bijection).
+  const int t = xcd_contiguous(blockIdx.x, gridDim.x);
   int ti, tj;
   if (tiles == kTilesNext) {
-    ti = blockIdx.x;
+    ti = t;
     tj = 0;
   } else {
-    tri_index(blockIdx.x, ti, tj);
+    tri_index(t, ti, tj);
     if (tiles == kTilesRest) {
       ++ti;
       ++tj;
@@ -229,15 +359,32 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
   const int wr = w >> 1, wc = w & 1;
   const bool active = !(ti == tj && wr < wc);
 
+  acc_t acc[4][4];
+  // C tile prefetch (rows i, columns j of this lane's result registers)
+  double cv[4][4][4];
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc[bj][bi][r] = 0;
+        const int64_t i = row0 + 64 * wr + 16 * bi + lr;
+        const int64_t j = col0 + 64 * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
+        cv[bj][bi][r] = (active && i < m && j < m && i >= j) ? C[j * ld + i] : 0.0;
+      }
+
   T ra[NLD], rb[NLD];
   auto gload = [&](int kk) {
 #pragma unroll
     for (int q = 0; q < NLD; ++q) {
       const int e = tid + 256 * q;
       const int kc = e / kTS, r = e % kTS;
-      const int64_t ia = row0 + r, ib = col0 + r;
-      ra[q] = (ia < m) ? L[(int64_t)(kk + kc) * ldl + ia] : T(0);
-      rb[q] = (ib < m) ? L[(int64_t)(kk + kc) * ldl + ib] : T(0);
+      // rows past m are clamped (their products only reach masked outputs)
+      const int64_t ia = (row0 + r < m) ? row0 + r : m - 1;
+      const int64_t ib = (col0 + r < m) ? col0 + r : m - 1;
+      ra[q] = L[(int64_t)(kk + kc) * ldl + ia];
+      rb[q] = L[(int64_t)(kk + kc) * ldl + ib];
     }
   };
   auto sstore = [&](int buf) {
@@ -250,21 +397,13 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
     }
   };
 
-  acc_t acc[4][4];
-#pragma unroll
-  for (int bj = 0; bj < 4; ++bj)
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[bj][bi][r] = 0;
-
-  const int nch = NB / KC;
+  constexpr int nch = NB / KC;
   gload(0);
   sstore(0);
+  if (nch > 1) gload(KC);
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
-    if (ch + 1 < nch) gload((ch + 1) * KC);
     if (active) {
 #pragma unroll
       for (int kq = 0; kq < KC / 4; ++kq) {
@@ -279,7 +418,10 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
           for (int bi = 0; bi < 4; ++bi) acc[bj][bi] = mfma(af[bj], bf[bi], acc[bj][bi]);
       }
     }
-    if (ch + 1 < nch) sstore(buf ^ 1);
+    if (ch + 1 < nch) {
+      sstore(buf ^ 1);                       // chunk ch+1, loaded one iteration ago
+      if (ch + 2 < nch) gload((ch + 2) * KC);  // two chunks ahead
+    }
     __syncthreads();
   }
   if (!active) return;
@@ -291,14 +433,14 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
       for (int r = 0; r < 4; ++r) {
         const int64_t i = row0 + 64 * wr + 16 * bi + lr;
         const int64_t j = col0 + 64 * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
-        if (i < m && j < m && i >= j) C[j * ld + i] -= (double)acc[bj][bi][r];
+        if (i < m && j < m && i >= j) C[j * ld + i] = cv[bj][bi][r] - (double)acc[bj][bi][r];
       }
 }
 
 }  // namespace
 
 size_t cholesky_workspace_bytes(int64_t n, bd_precision_t prec) {
-  size_t b = align_up(sizeof(double) * NB * NB, 256);
+  size_t b = align_up(sizeof(double) * NB * NB, 256);  // four 32 x 32 inverses (NB*NB/4 used)
   if (prec == BD_PREC_MIXED) b += 2 * align_up(sizeof(float) * (size_t)n * NB, 256);
   return b;
 }
@@ -320,7 +462,7 @@ hipError_t factor_panel(const CholCtx& c, hipStream_t s, int64_t k) {
   const int64_t m = c.n - k - nb;
   if (m > 0) {
     float* P = c.P32[(k / NB) & 1];
-    BD_LAUNCH("panel_solve", panel_solve_kernel, dim3((unsigned)((m + kRB - 1) / kRB)), dim3(256),
+    BD_LAUNCH("panel_solve", panel_solve_kernel, dim3((unsigned)((m + kRB - 1) / kRB)), dim3(kPsThreads),
               0, s, c.A, c.ld, k, nb, m, c.W, P, c.n);
   }
   return hipGetLastError();

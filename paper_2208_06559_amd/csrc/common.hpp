@@ -51,7 +51,8 @@ hipError_t launch_predictor(hipStream_t s, const bd_params_t& p, const double* x
 // constrain.hip
 size_t constrain_workspace_bytes(int64_t n_beads);
 hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x_old, double* xs,
-                            double* T_out, void* ws, DevState* st, DevState* host_state_pinned);
+                            double* T_out, void* ws, DevState* st, DevState* host_state_pinned,
+                            int* pairs_hint);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

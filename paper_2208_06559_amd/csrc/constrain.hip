@@ -11,10 +11,9 @@
 // D_{k+1,l} - D_{k,l+1} + D_{k,l}.  Every product with D is matrix-free.
 //
 // Device work is split in two kernels that the host launches alternately:
-//   dmatvec     r = D f over all bead pairs, many workgroups, partial sums
-//               per column chunk (no atomics, fixed reduction order);
-//   controller  one workgroup of 1024 threads: reduces the partial sums and
-//               advances the Newton/GMRES state machine by one matrix-vector
+//   dmatvec     r = D f over all bead pairs, one workgroup per 16 beads i
+//               (no atomics, fixed reduction order);
+//   controller  one workgroup of 512 threads: advances the Newton/GMRES state machine by one matrix-vector
 //               product (residual check, band Jacobian, Arnoldi step, PCR
 //               tridiagonal solve in LDS), then writes the next f.
 // Once the iteration has finished both kernels return immediately.
@@ -27,10 +26,9 @@ namespace bd {
 namespace {
 
 constexpr int kKmax = 60;          // GMRES iterations per Newton step
-constexpr int kCtlThreads = 1024;  // controller workgroup
+constexpr int kCtlThreads = 512;   // controller workgroup
 constexpr int kMaxRods = 4096;     // LDS capacity of the tridiagonal solve
-constexpr int kMvI = 64;           // beads i per matvec workgroup
-constexpr int kMvChunk = 256;      // max beads j per matvec workgroup
+constexpr int kMvI = 16;           // beads i per matvec workgroup
 
 enum { PH_RESID = 0, PH_KRYLOV = 1 };
 
@@ -44,25 +42,13 @@ struct NewtonCtl {
 };
 
 struct Bufs {
-  double *u, *Qs, *Q, *Gd, *Gp, *Gm, *T, *lo, *di, *up, *rhs, *z, *f, *r, *part, *V, *H, *cs, *sn,
-      *s, *y;
+  double *u, *Qs, *Q, *Gd, *Gp, *Gm, *T, *lo, *di, *up, *rhs, *z, *f, *r, *V, *H, *cs, *sn, *s, *y;
   NewtonCtl* ctl;
 };
 
-__host__ __device__ inline int mv_chunks(int N) {
-  const int iblocks = (N + kMvI - 1) / kMvI;
-  int jc = (2048 + iblocks - 1) / iblocks;
-  const int jmin = (N + kMvChunk - 1) / kMvChunk;
-  const int jmax = (N + 31) / 32;
-  if (jc > jmax) jc = jmax;
-  if (jc < jmin) jc = jmin;
-  if (jc < 1) jc = 1;
-  return jc;
-}
 
 Bufs carve(void* ws, int N) {
   const int64_t M = N - 1;
-  const int JC = mv_chunks(N);
   char* p = static_cast<char*>(ws);
   auto take = [&](size_t count) {
     double* q = reinterpret_cast<double*>(p);
@@ -84,7 +70,6 @@ Bufs carve(void* ws, int N) {
   b.z = take(M);
   b.f = take(3 * (size_t)N);
   b.r = take(3 * (size_t)N);
-  b.part = take((size_t)JC * 3 * N);
   b.V = take((size_t)(kKmax + 1) * M);
   b.H = take((size_t)(kKmax + 1) * kKmax);
   b.cs = take(kKmax);
@@ -98,6 +83,49 @@ Bufs carve(void* ws, int N) {
 size_t carve_bytes(int N) {
   Bufs b = carve(nullptr, N);
   return reinterpret_cast<size_t>(b.ctl) + 256;
+}
+
+// RPY coefficients (Eqs. 8-9) for the matrix-free products, without
+// divisions: 1/R from the hardware estimate refined by two Newton steps.
+struct RpyConst {
+  double a2x2;      // (2a)^2, the near/far threshold on R^2
+  double far_pre;   // 3 h*/4
+  double a2;        // a^2
+  double near_pre;  // 3 h*/(8a)
+  double near_r;    // 3/(4a)
+  double near_rr;   // 3 h*/(8a) / (4a)
+};
+
+RpyConst rpy_const(double hstar, double a) {
+  RpyConst c;
+  c.a2x2 = 4.0 * a * a;
+  c.far_pre = 0.75 * hstar;
+  c.a2 = a * a;
+  c.near_pre = 3.0 * hstar / (8.0 * a);
+  c.near_r = 3.0 / (4.0 * a);
+  c.near_rr = c.near_pre / (4.0 * a);
+  return c;
+}
+
+__device__ __forceinline__ void rpy_coeffs_fast(double R2, const RpyConst& k, double& cI,
+                                                double& cRR) {
+  double y = __builtin_amdgcn_rsq(R2);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double h = 0.5 * R2 * y;
+    y = fma(-h, y, 1.5) * y;
+  }
+  const double inv2 = y * y;
+  if (R2 >= k.a2x2) {
+    const double pre = k.far_pre * y;
+    const double t = k.a2 * inv2;
+    cI = pre * (1.0 + (2.0 / 3.0) * t);
+    cRR = pre * (1.0 - 2.0 * t) * inv2;
+  } else {
+    const double R = (R2 > 0.0) ? R2 * y : 0.0;  // coincident beads: the R -> 0 limit
+    cI = k.near_pre * (8.0 / 3.0 - k.near_r * R);
+    cRR = (R2 > 0.0) ? k.near_rr * y : 0.0;
+  }
 }
 
 // D_ij applied to v: identity for i == j, RPY block otherwise.
@@ -142,7 +170,7 @@ __device__ __forceinline__ void unit_bond(const double* __restrict__ x, int k, d
 
 __global__ __launch_bounds__(256) void constrain_init_kernel(const double* __restrict__ x_old,
                                                               const double* __restrict__ xs,
-                                                              Bufs b, int N, int JC, double hstar,
+                                                              Bufs b, int N, double hstar,
                                                               double a, DevState* st) {
   const int M = N - 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -175,8 +203,7 @@ __global__ __launch_bounds__(256) void constrain_init_kernel(const double* __res
     }
     for (int al = 0; al < 3; ++al) b.Gm[3 * k + al] = o[al];
   }
-  const int64_t np = (int64_t)JC * 3 * N;
-  for (int64_t e = t; e < np; e += (int64_t)gridDim.x * blockDim.x) b.part[e] = 0.0;
+  for (int64_t e = t; e < 3 * (int64_t)N; e += (int64_t)gridDim.x * blockDim.x) b.r[e] = 0.0;
   if (t == 0) {
     b.ctl->phase = PH_RESID;
     b.ctl->j = 0;
@@ -188,53 +215,72 @@ __global__ __launch_bounds__(256) void constrain_init_kernel(const double* __res
   }
 }
 
-// r = D f over the column chunk blockIdx.y; partial sums to part[jc][3N].
-__global__ __launch_bounds__(256) void dmatvec_kernel(const double* __restrict__ x,
+// r = D f.  A workgroup of 16 waves owns kMvI = 16 beads i and sweeps every
+// bead j: lane (il, jp) = (lane % 16, lane / 16) of wave w takes phase
+// 4w + jp, i.e. j = phase, phase + 64, ...; the 64 phase sums of each r_i are
+// then added in a fixed order (no atomics, no cross-workgroup traffic,
+// bitwise reproducible).  16 waves per workgroup keep four waves on each
+// SIMD to hide the FP64 latencies.
+constexpr int kMvThreads = 1024;
+constexpr int kMvWaves = kMvThreads / 64;
+
+__global__ __launch_bounds__(kMvThreads) void dmatvec_kernel(const double* __restrict__ x,
                                                        const double* __restrict__ f,
-                                                       double* __restrict__ part, int N, int chunk,
-                                                       double hstar, double a,
+                                                       double* __restrict__ r, int N, RpyConst kc,
                                                        const DevState* __restrict__ st) {
   if (st->done) return;
-  __shared__ double sx[3 * kMvChunk], sf[3 * kMvChunk];
-  __shared__ double red[4][3][kMvI];
+  constexpr int kChunk = 512;  // beads j staged in LDS per round
+  __shared__ double sx[3 * kChunk], sf[3 * kChunk];
+  __shared__ double red[kMvWaves][3][kMvI];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int jc = blockIdx.y;
-  const int j0 = jc * chunk;
-  const int j1 = (j0 + chunk < N) ? j0 + chunk : N;
-  for (int e = tid; e < 3 * (j1 - j0); e += 256) {
-    sx[e] = x[3 * j0 + e];
-    sf[e] = f[3 * j0 + e];
-  }
-  __syncthreads();
-  const int i = blockIdx.x * kMvI + lane;
+  const int il = lane & 15, jp = lane >> 4;
+  const int i = blockIdx.x * kMvI + il;
+  const int ii = (i < N) ? i : N - 1;
+  const double xi0 = x[3 * ii], xi1 = x[3 * ii + 1], xi2 = x[3 * ii + 2];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  if (i < N) {
-    const double xi0 = x[3 * i], xi1 = x[3 * i + 1], xi2 = x[3 * i + 2];
-    for (int jj = j0 + w; jj < j1; jj += 4) {
-      const int q = 3 * (jj - j0);
+  for (int j0 = 0; j0 < N; j0 += kChunk) {
+    const int nj = (N - j0 < kChunk) ? N - j0 : kChunk;
+    __syncthreads();
+    for (int e = tid; e < 3 * nj; e += kMvThreads) {
+      sx[e] = x[3 * j0 + e];
+      sf[e] = f[3 * j0 + e];
+    }
+    __syncthreads();
+    for (int jj = 4 * w + jp; jj < nj; jj += 4 * kMvWaves) {
+      const int q = 3 * jj;
       const double f0 = sf[q], f1 = sf[q + 1], f2 = sf[q + 2];
-      if (jj == i) {
-        a0 += f0; a1 += f1; a2 += f2;
-      } else {
-        const double R0 = xi0 - sx[q], R1 = xi1 - sx[q + 1], R2c = xi2 - sx[q + 2];
-        double cI, cRR;
-        rpy_coeffs(R0 * R0 + R1 * R1 + R2c * R2c, hstar, a, cI, cRR);
-        const double rv = cRR * (R0 * f0 + R1 * f1 + R2c * f2);
-        a0 += cI * f0 + rv * R0;
-        a1 += cI * f1 + rv * R1;
-        a2 += cI * f2 + rv * R2c;
+      const double R0 = xi0 - sx[q], R1 = xi1 - sx[q + 1], R2c = xi2 - sx[q + 2];
+      double cI, cRR;
+      rpy_coeffs_fast(R0 * R0 + R1 * R1 + R2c * R2c, kc, cI, cRR);
+      if (j0 + jj == ii) {  // D_ii = I
+        cI = 1.0;
+        cRR = 0.0;
       }
+      const double rv = cRR * (R0 * f0 + R1 * f1 + R2c * f2);
+      a0 += cI * f0 + rv * R0;
+      a1 += cI * f1 + rv * R1;
+      a2 += cI * f2 + rv * R2c;
     }
   }
-  red[w][0][lane] = a0;
-  red[w][1][lane] = a1;
-  red[w][2][lane] = a2;
+  // phases jp = 0..3 of this wave: lanes il, il+16, il+32, il+48
+  a0 += __shfl_xor(a0, 16, 64);
+  a1 += __shfl_xor(a1, 16, 64);
+  a2 += __shfl_xor(a2, 16, 64);
+  a0 += __shfl_xor(a0, 32, 64);
+  a1 += __shfl_xor(a1, 32, 64);
+  a2 += __shfl_xor(a2, 32, 64);
+  if (jp == 0) {
+    red[w][0][il] = a0;
+    red[w][1][il] = a1;
+    red[w][2][il] = a2;
+  }
   __syncthreads();
-  if (w == 0 && i < N) {
-    double* out = part + (int64_t)jc * 3 * N + 3 * (int64_t)i;
-#pragma unroll
-    for (int al = 0; al < 3; ++al)
-      out[al] = ((red[0][al][lane] + red[1][al][lane]) + red[2][al][lane]) + red[3][al][lane];
+  if (tid < 3 * kMvI) {
+    const int al = tid / kMvI, b = tid % kMvI;
+    const int ib = blockIdx.x * kMvI + b;
+    double acc = 0.0;
+    for (int q = 0; q < kMvWaves; ++q) acc += red[q][al][b];
+    if (ib < N) r[3 * ib + al] = acc;
   }
 }
 
@@ -275,6 +321,24 @@ __device__ double block_max(double v, double* red) {
   for (int q = 1; q < kCtlThreads / 64; ++q) s = nanmax(s, red[q]);
   __syncthreads();
   return s;
+}
+
+// Eight block sums at once (fixed order); every thread gets the results.
+__device__ void block_sum8(double v[8], double (*red8)[8]) {
+  const int tid = threadIdx.x, w = tid >> 6;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) v[u] = wave_sum(v[u]);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) red8[w][u] = v[u];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    double s = 0.0;
+    for (int q = 0; q < kCtlThreads / 64; ++q) s += red8[q][u];
+    v[u] = s;
+  }
+  __syncthreads();
 }
 
 // Parallel cyclic reduction (Hockney) for the tridiagonal system
@@ -344,21 +408,17 @@ __device__ void rod_forces(const double* __restrict__ z, const double* __restric
 }
 
 __global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
-    Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, int JC, double dt,
+    Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, double dt,
     double bl, double tol, int maxit, DevState* __restrict__ st) {
   __shared__ double pa[kMaxRods], pb[kMaxRods], pc[kMaxRods], pd[kMaxRods];
   __shared__ double red[kCtlThreads / 64];
+  __shared__ double red8[kCtlThreads / 64][8];
+  __shared__ double hcur[kKmax + 1], hsum[kKmax + 1];
   __shared__ int sh_flag;
   if (st->done) return;
   const int tid = threadIdx.x;
   const int M = N - 1;
   const int64_t n3 = 3 * (int64_t)N;
-  for (int64_t e = tid; e < n3; e += kCtlThreads) {
-    double s = 0.0;
-    for (int q = 0; q < JC; ++q) s += b.part[(int64_t)q * n3 + e];
-    b.r[e] = s;
-  }
-  __syncthreads();
   NewtonCtl* ctl = b.ctl;
   const int phase = ctl->phase;
   if (phase == PH_RESID) {
@@ -439,20 +499,43 @@ __global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
     w[k] = 2.0 * dt * (q[0] * d0 + q[1] * d1 + q[2] * d2);
   }
   __syncthreads();
-  for (int i = 0; i <= j; ++i) {
-    const double* vi = b.V + (int64_t)i * M;
-    double part = 0.0;
-    for (int k = tid; k < M; k += kCtlThreads) part += w[k] * vi[k];
-    const double h = block_sum(part, red);
-    if (tid == 0) b.H[i * kKmax + j] = h;
-    for (int k = tid; k < M; k += kCtlThreads) w[k] -= h * vi[k];
+  // Classical Gram-Schmidt with one re-orthogonalisation: each pass forms
+  // every projection h_i = <w, v_i> (block reductions of 8 at a time), then
+  // w -= sum_i h_i v_i.
+  for (int i = tid; i <= j; i += kCtlThreads) hsum[i] = 0.0;
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i0 = 0; i0 <= j; i0 += 8) {
+      double pr[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pr[u] = 0.0;
+      for (int k = tid; k < M; k += kCtlThreads) {
+        const double wk = w[k];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (i0 + u <= j) pr[u] += wk * b.V[(int64_t)(i0 + u) * M + k];
+      }
+      block_sum8(pr, red8);
+      if (tid < 8 && i0 + tid <= j) {
+        hcur[i0 + tid] = pr[tid];
+        hsum[i0 + tid] += pr[tid];
+      }
+      __syncthreads();
+    }
+    for (int k = tid; k < M; k += kCtlThreads) {
+      double acc = 0.0;
+      for (int i = 0; i <= j; ++i) acc += hcur[i] * b.V[(int64_t)i * M + k];
+      w[k] -= acc;
+    }
     __syncthreads();
   }
+  if (tid <= j) b.H[tid * kKmax + j] = hsum[tid];
   double part = 0.0;
   for (int k = tid; k < M; k += kCtlThreads) part += w[k] * w[k];
   const double hn = sqrt(block_sum(part, red));
   if (hn > 0.0)
     for (int k = tid; k < M; k += kCtlThreads) w[k] /= hn;
+  __syncthreads();
   if (tid == 0) {
     double* H = b.H;
     H[(j + 1) * kKmax + j] = hn;
@@ -512,36 +595,45 @@ size_t constrain_workspace_bytes(int64_t n_beads) { return carve_bytes((int)n_be
 int constrain_max_beads() { return kMaxRods + 1; }
 
 hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x_old, double* xs,
-                            double* T_out, void* ws, DevState* st, DevState* host_state) {
+                            double* T_out, void* ws, DevState* st, DevState* host_state,
+                            int* pairs_hint) {
   const int N = p.n_beads;
   const int M = N - 1;
-  const int JC = mv_chunks(N);
-  const int chunk = (N + JC - 1) / JC;
   Bufs b = carve(ws, N);
   const int ithreads = M > 0 ? M : 1;
   int iblk = (ithreads + 255) / 256;
   if (iblk < 16) iblk = 16;
-  BD_LAUNCH("constrain_init", constrain_init_kernel, dim3(iblk), dim3(256), 0, s, x_old, xs, b, N, JC,
-                     p.hstar, p.a, st);
-  BD_LAUNCH("newton_controller", newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b, xs, T_out, N,
-                     JC, p.dt, p.b, p.newton_tol, p.newton_maxit, st);
-  const dim3 mvgrid((N + kMvI - 1) / kMvI, JC);
+  BD_LAUNCH("constrain_init", constrain_init_kernel, dim3(iblk), dim3(256), 0, s, x_old, xs, b, N,
+            p.hstar, p.a, st);
+  BD_LAUNCH("newton_controller", newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b, xs,
+            T_out, N, p.dt, p.b, p.newton_tol, p.newton_maxit, st);
+  const dim3 mvgrid((N + kMvI - 1) / kMvI);
+  const RpyConst kc = rpy_const(p.hstar, p.a);
+  // Each (matvec, controller) pair advances the iteration by one product with
+  // D.  The first batch is sized from the previous call's count, then the
+  // host polls the device flag after every further small batch; launches
+  // after convergence return at once.
   const int cap = (p.newton_maxit + 1) * (kKmax + 2);
-  constexpr int kPoll = 8;
-  for (int done = 0; done < cap; done += kPoll) {
-    for (int c = 0; c < kPoll; ++c) {
-      BD_LAUNCH("dmatvec", dmatvec_kernel, mvgrid, dim3(256), 0, s, x_old, b.f, b.part, N, chunk,
-                         p.hstar, p.a, st);
-      BD_LAUNCH("newton_controller", newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b, xs, T_out,
-                         N, JC, p.dt, p.b, p.newton_tol, p.newton_maxit, st);
+  int batch = (pairs_hint && *pairs_hint > 0) ? *pairs_hint + 1 : 8;
+  int launched = 0;
+  while (launched < cap) {
+    if (batch > cap - launched) batch = cap - launched;
+    for (int c = 0; c < batch; ++c) {
+      BD_LAUNCH("dmatvec", dmatvec_kernel, mvgrid, dim3(kMvThreads), 0, s, x_old, b.f, b.r, N, kc,
+                st);
+      BD_LAUNCH("newton_controller", newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b,
+                xs, T_out, N, p.dt, p.b, p.newton_tol, p.newton_maxit, st);
     }
-    hipError_t e = hipMemcpyAsync(&host_state->done, &st->done, sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, s);
+    launched += batch;
+    hipError_t e = hipMemcpyAsync(host_state, st, sizeof(DevState), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
     if (host_state->done) break;
+    batch = 4;
   }
+  if (pairs_hint && host_state->done)
+    *pairs_hint = host_state->newton_iters + host_state->krylov_iters;
   return hipGetLastError();
 }
 
