@@ -57,6 +57,8 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
 // Row of the 16 x 16 result held by register r of a lane with lane/16 = lk.
 __device__ __forceinline__ int res_row(d4, int lk, int r) { return lk + 4 * r; }
 __device__ __forceinline__ int res_row(f4, int lk, int r) { return 4 * lk + r; }
+// the FP64 result layout above, as a compile-time fact for register-resident code
+constexpr bool res_row_f64_is_lk_plus_4r = true;
 
 // ------------------------------------------------------------------------
 // 1. Diagonal block (NB x NB, FP64, one workgroup of 256 threads).
@@ -92,8 +94,9 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
 // constant).
 template <int JB>
 __device__ __forceinline__ void chol_block(double (&a)[TT][TT], double* __restrict__ col,
-                                           double* __restrict__ piv, int tr, int tc, int tid,
-                                           int64_t k, DevState* __restrict__ st) {
+                                           double* __restrict__ piv, double* __restrict__ rdg,
+                                           int tr, int tc, int tid, int64_t k,
+                                           DevState* __restrict__ st) {
   for (int jr = 0; jr < 16; ++jr) {
     const int j = 16 * JB + jr;
     __syncthreads();  // pivot published; previous column no longer read
@@ -110,6 +113,7 @@ __device__ __forceinline__ void chol_block(double (&a)[TT][TT], double* __restri
         if (i == j) {
           a[ia][JB] = d * rs;
           col[i] = a[ia][JB];
+          rdg[j] = rs;  // 1 / L(j,j), used by the diagonal-block inversion
         } else if (i > j) {
           a[ia][JB] *= rs;
           col[i] = a[ia][JB];
@@ -157,6 +161,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
   __shared__ double piv;              // the current pivot
   __shared__ double Ld[NSB][SBB];     // diagonal 32 x 32 blocks of L, column-major
   __shared__ double rowb[4][SB];      // per-wave row broadcast of the inversions
+  __shared__ double rdg[NB];          // 1 / L(j,j)
   const int tid = threadIdx.x;
   const int tr = tid & 15, tc = tid >> 4;
   double* Akk = A + k * ld + k;
@@ -176,14 +181,14 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
     }
   if (tid == 0) piv = a[0][0];
   static_assert(TT == 8, "diagonal block tiling");
-  chol_block<0>(a, col, &piv, tr, tc, tid, k, st);
-  chol_block<1>(a, col, &piv, tr, tc, tid, k, st);
-  chol_block<2>(a, col, &piv, tr, tc, tid, k, st);
-  chol_block<3>(a, col, &piv, tr, tc, tid, k, st);
-  chol_block<4>(a, col, &piv, tr, tc, tid, k, st);
-  chol_block<5>(a, col, &piv, tr, tc, tid, k, st);
-  chol_block<6>(a, col, &piv, tr, tc, tid, k, st);
-  chol_block<7>(a, col, &piv, tr, tc, tid, k, st);
+  chol_block<0>(a, col, &piv, rdg, tr, tc, tid, k, st);
+  chol_block<1>(a, col, &piv, rdg, tr, tc, tid, k, st);
+  chol_block<2>(a, col, &piv, rdg, tr, tc, tid, k, st);
+  chol_block<3>(a, col, &piv, rdg, tr, tc, tid, k, st);
+  chol_block<4>(a, col, &piv, rdg, tr, tc, tid, k, st);
+  chol_block<5>(a, col, &piv, rdg, tr, tc, tid, k, st);
+  chol_block<6>(a, col, &piv, rdg, tr, tc, tid, k, st);
+  chol_block<7>(a, col, &piv, rdg, tr, tc, tid, k, st);
   // L11 to global (lower part) and the diagonal blocks to LDS
 #pragma unroll
   for (int ia = 0; ia < TT; ++ia)
@@ -202,11 +207,11 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
 #pragma unroll
     for (int c = 0; c < 16; ++c) w[c] = (r == 16 * h + c) ? 1.0 : 0.0;
     for (int q = 0; q < SB; ++q) {
-      const double lqq = L[q * SB + q];
+      const double rq = rdg[SB * p + q];
       if (r == q) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-          w[c] = w[c] / lqq;
+          w[c] = w[c] * rq;
           rowb[p][16 * h + c] = w[c];
         }
       }
@@ -230,70 +235,79 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
 // 2. Panel solve X L11^T = A21 for a block of 32 rows, by blocked forward
 //    substitution over the four 32-column sub-panels:
 //      X(:,p) = (A(:,p) - sum_{q<p} X(:,q) L11(p,q)^T) Winv_p^T.
-//    Two waves, 16 rows each; the row block lives in LDS, so the result can
-//    overwrite A21 in place.  In MIXED mode an FP32 copy is stored as well.
+//    Two waves, 16 rows each, and no LDS: with the rows of X as the MFMA
+//    B operand, lane (lr, lk) needs exactly the columns c = lk (mod 4) of
+//    row lr, which are also the columns the MFMA result leaves in that lane,
+//    so the row block stays in registers (x[t] = column 4t + lk).  The L11
+//    and Winv operands come straight from global memory (L2-resident).
+//    In MIXED mode an FP32 copy of X is stored as well.
 // ------------------------------------------------------------------------
 constexpr int kRB = 32;          // rows per panel-solve workgroup
 constexpr int kPsThreads = 128;  // two waves
 
+template <int P>
+__device__ __forceinline__ void solve_subpanel(double (&x)[NB / 4], const double* __restrict__ L11,
+                                               int64_t ld, const double* __restrict__ Wp, int lr,
+                                               int lk) {
+  constexpr int c0 = SB * P;
+  // operands first (one round trip), then the MFMA chains
+  double la[2][c0 / 4 + 1], wa[2][SB / 4];
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt) {
+#pragma unroll
+    for (int s = 0; s < c0 / 4; ++s) la[jt][s] = L11[(int64_t)(4 * s + lk) * ld + c0 + 16 * jt + lr];
+#pragma unroll
+    for (int s = 0; s < SB / 4; ++s) wa[jt][s] = Wp[(4 * s + lk) * SB + 16 * jt + lr];
+  }
+  if (c0 > 0) {
+    d4 acc[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
+#pragma unroll
+    for (int s = 0; s < c0 / 4; ++s)
+#pragma unroll
+      for (int jt = 0; jt < 2; ++jt) acc[jt] = mfma(la[jt][s], x[s], acc[jt]);
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[c0 / 4 + 4 * jt + q] -= acc[jt][q];
+  }
+  d4 y[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
+#pragma unroll
+  for (int s = 0; s < SB / 4; ++s)
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) y[jt] = mfma(wa[jt][s], x[c0 / 4 + s], y[jt]);
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[c0 / 4 + 4 * jt + q] = y[jt][q];
+}
+
 __global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
     double* __restrict__ A, int64_t ld, int64_t k, int nb, int64_t m, const double* __restrict__ W,
     float* __restrict__ P32, int64_t ldp) {
-  __shared__ double Xs[NB][kRB + 4];  // Xs[col][row]
-  __shared__ double Ls[SB][NB + 4];   // Ls[c][q] = L11[32p + c][q], q < 32p
-  __shared__ double Ws[SB][SB + 4];   // Ws[c][r] = Winv_p[r][c]
+  static_assert(NSB == 4 && res_row_f64_is_lk_plus_4r, "register layout of the panel solve");
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.x * kRB;
+  const int64_t row = (int64_t)blockIdx.x * kRB + 16 * w + lr;
+  const bool live = row < m;
   double* A21 = A + k * ld + k + nb;
   const double* L11 = A + k * ld + k;
-  for (int idx = tid; idx < NB * kRB; idx += kPsThreads) {
-    const int kk = idx / kRB, r = idx % kRB;
-    const int64_t row = r0 + r;
-    Xs[kk][r] = (kk < nb && row < m) ? A21[(int64_t)kk * ld + row] : 0.0;
+  double x[NB / 4];
+#pragma unroll
+  for (int t = 0; t < NB / 4; ++t) {
+    const int c = 4 * t + lk;
+    x[t] = (live && c < nb) ? A21[(int64_t)c * ld + row] : 0.0;
   }
-  const int i0 = 16 * w;
-  for (int p = 0; p < NSB; ++p) {
-    const int c0 = SB * p;
-    __syncthreads();  // previous sub-panel done with Ls/Ws
-    for (int idx = tid; idx < SB * c0; idx += kPsThreads) {
-      const int q = idx / SB, c = idx % SB;
-      Ls[c][q] = (c0 + c < nb && q < nb) ? L11[(int64_t)q * ld + c0 + c] : 0.0;
-    }
-    for (int idx = tid; idx < SBB; idx += kPsThreads) Ws[idx / SB][idx % SB] = W[p * SBB + idx];
-    __syncthreads();
-    // T = A(:,p) - X(:,0:c0) L11(p, 0:c0)^T
-    d4 acc[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
-    for (int kk = 0; kk < c0; kk += 4) {
-      const double b = Xs[kk + lk][i0 + lr];
+  solve_subpanel<0>(x, L11, ld, W, lr, lk);
+  solve_subpanel<1>(x, L11, ld, W + SBB, lr, lk);
+  solve_subpanel<2>(x, L11, ld, W + 2 * SBB, lr, lk);
+  solve_subpanel<3>(x, L11, ld, W + 3 * SBB, lr, lk);
+  if (!live) return;
 #pragma unroll
-      for (int jt = 0; jt < 2; ++jt) acc[jt] = mfma(Ls[16 * jt + lr][kk + lk], b, acc[jt]);
-    }
-#pragma unroll
-    for (int jt = 0; jt < 2; ++jt)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Xs[c0 + 16 * jt + res_row(acc[jt], lk, q)][i0 + lr] -= acc[jt][q];
-    // X(:,p) = T Winv_p^T (rows of this wave only, in place)
-    d4 x[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
-#pragma unroll
-    for (int kk = 0; kk < SB; kk += 4) {
-      const double b = Xs[c0 + kk + lk][i0 + lr];
-#pragma unroll
-      for (int jt = 0; jt < 2; ++jt) x[jt] = mfma(Ws[kk + lk][16 * jt + lr], b, x[jt]);
-    }
-#pragma unroll
-    for (int jt = 0; jt < 2; ++jt)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Xs[c0 + 16 * jt + res_row(x[jt], lk, q)][i0 + lr] = x[jt][q];
-  }
-  __syncthreads();
-  for (int idx = tid; idx < NB * kRB; idx += kPsThreads) {
-    const int kk = idx / kRB, r = idx % kRB;
-    const int64_t row = r0 + r;
-    if (kk < nb && row < m) {
-      const double v = Xs[kk][r];
-      A21[(int64_t)kk * ld + row] = v;
-      if (P32) P32[(int64_t)kk * ldp + row] = (float)v;
+  for (int t = 0; t < NB / 4; ++t) {
+    const int c = 4 * t + lk;
+    if (c < nb) {
+      A21[(int64_t)c * ld + row] = x[t];
+      if (P32) P32[(int64_t)c * ldp + row] = (float)x[t];
     }
   }
 }
@@ -460,7 +474,7 @@ hipError_t factor_panel(const CholCtx& c, hipStream_t s, int64_t k) {
   BD_LAUNCH("potrf_diag", potrf_diag_kernel, dim3(1), dim3(256), 0, s, c.A, c.ld, k, nb, c.W,
             c.st);
   const int64_t m = c.n - k - nb;
-  if (m > 0) {
+  if (m > 0) {  // then nb == NB: only the last panel can be narrower
     float* P = c.P32[(k / NB) & 1];
     BD_LAUNCH("panel_solve", panel_solve_kernel, dim3((unsigned)((m + kRB - 1) / kRB)), dim3(kPsThreads),
               0, s, c.A, c.ld, k, nb, m, c.W, P, c.n);
