@@ -37,21 +37,100 @@ def chol_flops(n: int) -> float:
     return n**3 / 3.0 + n**2 / 2.0 + n / 6.0
 
 
-def syrk_flops_per_factor(n: int, nb: int) -> tuple[float, int]:
-    """Algorithmic flops of the lower trailing updates (2 per multiply-add
-    over the m(m+1)/2 lower elements, rank nb) and their launch count: with
-    lookahead each panel's update is two launches, the next tile column and
-    (when there is more than one tile column) the rest."""
-    tot, cnt = 0.0, 0
-    k = 0
-    while k < n:
-        w = min(nb, n - k)
-        m = n - k - w
-        if m > 0:
-            tot += m * (m + 1) * w
-            cnt += 1 + (1 if m > nb else 0)
-        k += nb
-    return tot, cnt
+def syrk_launches(n: int, nb: int = 128, step_panels: int = 2) -> list[tuple[float, float, int]]:
+    """Every trailing-update launch of one factorisation in the library's
+    schedule (steps of `step_panels` panels with lookahead): per launch
+    (flops, lower elements updated, operand rows, kdim) with flops = 2 per
+    multiply-add over the lower elements of the tiles it updates."""
+    step = step_panels * nb
+    out = []
+
+    def trailing(r0, kdim, tiles, nnext):
+        m = n - r0
+        mt = -(-m // nb)
+        nnext = min(nnext, mt)
+        if tiles == "next":
+            nt = sum(mt - q for q in range(nnext))
+            elems = 0
+            for q in range(nnext):
+                wq = min(nb, m - nb * q)
+                elems += (m - nb * q) * wq - wq * (wq - 1) // 2
+            rows = m
+        elif tiles == "rest":
+            nt = (mt - nnext) * (mt - nnext + 1) // 2
+            m2 = m - nb * nnext
+            elems, rows = m2 * (m2 + 1) // 2, m2
+        else:
+            nt = mt * (mt + 1) // 2
+            elems, rows = m * (m + 1) // 2, m
+        if nt > 0:
+            out.append((2.0 * elems * kdim, float(elems), rows, kdim))
+
+    def factor_step(k0):
+        kp, p = k0, 0
+        while p < step_panels and kp < n:
+            if p > 0:
+                trailing(kp, kp - k0, "next", 1)
+            p += 1
+            kp += nb
+        return kp - k0
+
+    w, k = factor_step(0), 0
+    while k + w < n:
+        r0 = k + w
+        trailing(r0, w, "next", step // nb)
+        wn = factor_step(r0)
+        trailing(r0, w, "rest", step // nb)
+        k, w = r0, wn
+    return out
+
+
+def syrk_per_launch(n: int, esize: int) -> tuple[float, float, int]:
+    """Average algorithmic flops and HBM bytes per trailing-update launch,
+    and the launch count, of one factorisation.  Bytes: each updated lower
+    element of C read and written once in FP64 (16 B) plus each operand row
+    of L read once (kdim values of `esize` bytes)."""
+    sp = 1 if os.environ.get("BDRPY_STEP_PANELS", "").startswith("1") else 2
+    ls = syrk_launches(n, step_panels=sp)
+    fl = sum(x[0] for x in ls)
+    by = sum(16.0 * x[1] + x[2] * x[3] * esize for x in ls)
+    return fl / len(ls), by / len(ls), len(ls)
+
+
+COPY_PROBE_BYTES = 1 << 30
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "syrk_update_f32_n12288_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2208_06559_amd", "csrc", "cholesky.hip")
+
+
+def copy_probe(torch) -> int:
+    """Three device-to-device copies of COPY_PROBE_BYTES each: every copy
+    reads and writes that many bytes of HBM exactly once."""
+    src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "copies": 3}), flush=True)
+    return 0
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the kernel source changed since."""
+    import hashlib
+    try:
+        rec = None
+        with open(TRAFFIC_RECORD) as f:
+            for line in f:
+                if line.startswith("traffic_record: "):
+                    rec = json.loads(line[len("traffic_record: "):])
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel") != kernel or rec.get("source_sha256") != sha:
+        return None
+    return float(rec["hbm_bytes_per_launch"])
 
 
 def main() -> int:
@@ -66,6 +145,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", choices=["all", "mixed", "fp64"], default="all",
                     help="restrict the timed steps to one precision (for profiler runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of known size (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs one chain on one GPU; --gpus must be 1 "
@@ -74,6 +156,9 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        return copy_probe(torch)
 
     from paper_2208_06559_amd import binding as B
     from paper_2208_06559_amd import inputs as I
@@ -179,8 +264,6 @@ def main() -> int:
     torch.cuda.empty_cache()
 
     # ------------------------------------------- dominant-kernel roofline
-    nb = 128
-
     def profile(prec_name):
         pr = precs[prec_name]
         xx = x0.clone()
@@ -199,14 +282,22 @@ def main() -> int:
                    "share": v[1] / tot}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
         if kern.startswith("syrk_update"):
-            fl, cnt = syrk_flops_per_factor(n, nb)
+            f32 = kern.endswith("f32")
+            fl, by, cnt = syrk_per_launch(n, 4 if f32 else 8)
             assert launches == cnt * args.profile_steps, (launches, cnt)
-            achieved = fl * args.profile_steps / (kms * 1e-3) / 1e12
-            peak = PEAK_FP32 if kern.endswith("f32") else PEAK_FP64
-            rf = {"bound": "mfma", "kernel": kern, "achieved": achieved, "peak": peak,
-                  "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                  "algorithmic_flops_per_launch": fl / cnt, "avg_launch_ms": kms / launches,
-                  "launches": launches}
+            avg_s = kms * 1e-3 / launches
+            peak_fl = PEAK_FP32 if f32 else PEAK_FP64
+            # roofline: HBM-bound when the intensity is below the ridge point
+            if fl / by < peak_fl * 1e12 / (PEAK_HBM * 1e9):
+                achieved, peak, unit, bound = by / avg_s / 1e9, PEAK_HBM, "GB/s", "hbm"
+            else:
+                achieved, peak, unit, bound = fl / avg_s / 1e12, peak_fl, "TFLOP/s", "mfma"
+            rf = {"bound": bound, "kernel": kern, "achieved": achieved, "peak": peak,
+                  "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(kern),
+                  "algorithmic_flops_per_launch": fl, "algorithmic_bytes_per_launch": by,
+                  "intensity_flop_per_byte": fl / by,
+                  "tflops_per_launch_avg": fl / avg_s / 1e12,
+                  "avg_launch_ms": kms / launches, "launches": launches}
         else:
             rf = {"bound": "latency", "kernel": kern, "achieved": None, "peak": None,
                   "unit": None, "frac": None, "traffic": None,

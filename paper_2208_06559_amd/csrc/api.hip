@@ -27,6 +27,7 @@ struct bd_handle_s {
   int pairs_hint;      // D products the last tension solve needed
   hipStream_t aux;     // lookahead stream of the Cholesky (default priority)
   hipEvent_t ev[3];    // fork / panel-ready / rest-done events
+  int step_panels;     // Cholesky panels applied per pass over the trailing matrix
 };
 
 namespace {
@@ -151,6 +152,10 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   h->pairs_hint = 0;
   h->aux = nullptr;
   h->ev[0] = h->ev[1] = h->ev[2] = nullptr;
+  // BDRPY_STEP_PANELS=1 applies one panel per trailing pass (for
+  // comparisons); by default two panels share each pass over the matrix.
+  const char* sp = getenv("BDRPY_STEP_PANELS");
+  h->step_panels = (sp && sp[0] == '1') ? 1 : 2;
   if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
       hipHostMalloc(&h->host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
     release(h);
@@ -229,7 +234,8 @@ bd_status_t bd_cholesky(bd_handle_t h, int64_t n, double* d_A, int64_t ld, bd_pr
   if (n < 1 || !d_A || ld < n || !prec_ok(prec) || !d_ws) return BD_ERR_PARAM;
   if (ws_bytes < bd::cholesky_workspace_bytes(n, prec)) return BD_ERR_PARAM;
   if (reset(h) != hipSuccess) return BD_ERR_HIP;
-  return hip_status(bd::launch_cholesky(h->stream, h->aux, h->ev, n, d_A, ld, prec, d_ws, h->st));
+  return hip_status(bd::launch_cholesky(h->stream, h->aux, h->ev, n, d_A, ld, prec, d_ws, h->st,
+                                              h->step_panels));
 }
 
 bd_status_t bd_brownian(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_L,
@@ -276,7 +282,8 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
   hipError_t he = reset(h);
   if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
   if (he == hipSuccess)
-    he = bd::launch_cholesky(s, h->aux, h->ev, n, D, ld, prec, base + L.chol, h->st);
+    he = bd::launch_cholesky(s, h->aux, h->ev, n, D, ld, prec, base + L.chol, h->st,
+                              h->step_panels);
   if (he == hipSuccess)
     he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);

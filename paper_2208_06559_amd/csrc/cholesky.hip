@@ -89,67 +89,93 @@ __device__ __forceinline__ double rsqrt_refined(double d) {
   return y;
 }
 
-// Columns 16 JB .. 16 JB + 15 of the register-tiled factorisation (JB is a
-// template parameter so that every register index is a compile-time
-// constant).
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Column j = 16 IB + jn is held by the 16 threads tc == jn, which are 16
+// consecutive lanes of wave jn / 4; the pivot A(j,j) sits in the lane with
+// tr == tc == jn.  That wave reads the pivot across lanes (no LDS round
+// trip), the owners scale the column by 1/sqrt(pivot) and write it to the
+// LDS column buffer.  IB is a template parameter so that every register
+// index is a compile-time constant.
+template <int IB>
+__device__ __forceinline__ void publish_column(double (&a)[TT][TT], double* __restrict__ colv,
+                                               double* __restrict__ rdg, int jn, int tr, int tc,
+                                               int w, int64_t k, DevState* __restrict__ st) {
+  if (w != (jn >> 2)) return;  // wave-uniform
+  const int j = 16 * IB + jn;
+  const double d = readlane_f64(a[IB][IB], 16 * (jn & 3) + jn);
+  if (tc != jn) return;
+  if (tr == jn && !(d > 0.0) && st->potrf_info == 0) {
+    st->potrf_info = k + j + 1;
+    st->status = BD_ERR_NOT_SPD;
+  }
+  const double rs = rsqrt_refined(d);  // NaN for a non-positive pivot
+#pragma unroll
+  for (int ia = IB; ia < TT; ++ia) {
+    const int i = tr + 16 * ia;
+    if (i == j) {
+      a[ia][IB] = d * rs;
+      colv[i] = a[ia][IB];
+      rdg[j] = rs;  // 1 / L(j,j), used by the diagonal-block inversion
+    } else if (i > j) {
+      a[ia][IB] *= rs;
+      colv[i] = a[ia][IB];
+    }
+  }
+}
+
+// Rank-1 update by column j = 16 JB + jr (values ci, cc read from the
+// column buffer) of the tile columns IB0 <= ib < IB1.  Only tiles ib >= JB,
+// ia >= ib can hold live elements: for ia < ib every row is above every
+// column, for ia > ib every row is below; within ia == ib only tr >= tc;
+// and columns c > j need checking only at ib == JB.
+template <int JB, int IB0, int IB1>
+__device__ __forceinline__ void rank1_tiles(double (&a)[TT][TT], const double (&ci)[TT],
+                                            const double (&cc)[TT], int tr, int tc, int jr) {
+  const bool lower_diag = tr >= tc;
+  const bool col_live = tc > jr;  // column tc + 16 JB is past j
+#pragma unroll
+  for (int ib = IB0; ib < IB1; ++ib)
+#pragma unroll
+    for (int ia = ib; ia < TT; ++ia) {
+      bool live = true;
+      if (ia == ib) live = lower_diag;
+      if (ib == JB) live = live && col_live;
+      const double upd = fma(-ci[ia], cc[ib], a[ia][ib]);
+      a[ia][ib] = live ? upd : a[ia][ib];
+    }
+}
+
+// Columns 16 JB .. 16 JB + 15: with column j published in colbuf[j & 1],
+// every thread applies it to its live trailing elements, then the owners of
+// column j + 1 (just brought up to date) publish it into the other buffer;
+// one barrier per column.
 template <int JB>
-__device__ __forceinline__ void chol_block(double (&a)[TT][TT], double* __restrict__ col,
-                                           double* __restrict__ piv, double* __restrict__ rdg,
-                                           int tr, int tc, int tid, int64_t k,
-                                           DevState* __restrict__ st) {
+__device__ __forceinline__ void chol_block(double (&a)[TT][TT], double* __restrict__ colbuf,
+                                           double* __restrict__ rdg, int tr, int tc, int w,
+                                           int64_t k, DevState* __restrict__ st) {
+  constexpr int JN = (JB + 1 < TT) ? JB + 1 : JB;  // tile column of 16 (JB + 1)
   for (int jr = 0; jr < 16; ++jr) {
     const int j = 16 * JB + jr;
-    __syncthreads();  // pivot published; previous column no longer read
-    if (tc == jr) {
-      const double d = *piv;
-      if (tid == jr * 16 + jr && !(d > 0.0) && st->potrf_info == 0) {
-        st->potrf_info = k + j + 1;
-        st->status = BD_ERR_NOT_SPD;
-      }
-      const double rs = rsqrt_refined(d);  // NaN for a non-positive pivot
-#pragma unroll
-      for (int ia = JB; ia < TT; ++ia) {
-        const int i = tr + 16 * ia;
-        if (i == j) {
-          a[ia][JB] = d * rs;
-          col[i] = a[ia][JB];
-          rdg[j] = rs;  // 1 / L(j,j), used by the diagonal-block inversion
-        } else if (i > j) {
-          a[ia][JB] *= rs;
-          col[i] = a[ia][JB];
-        }
-      }
-    }
-    __syncthreads();  // column j of L published
-    // Only tiles ib >= JB, ia >= ib can hold live elements: for ia < ib every
-    // row is above every column; for ia > ib every row is below; within
-    // ia == ib only tr >= tc; and columns c > j need checking only at ib == JB.
+    const double* col = colbuf + (j & 1) * NB;
+    double* next = colbuf + ((j + 1) & 1) * NB;
     double ci[TT], cc[TT];
 #pragma unroll
     for (int ia = JB; ia < TT; ++ia) ci[ia] = col[tr + 16 * ia];
 #pragma unroll
     for (int ib = JB; ib < TT; ++ib) cc[ib] = col[tc + 16 * ib];
-    const bool lower_diag = tr >= tc;
-    const bool col_live = tc > jr;  // column tc + 16 JB is past j
-#pragma unroll
-    for (int ib = JB; ib < TT; ++ib)
-#pragma unroll
-      for (int ia = ib; ia < TT; ++ia) {
-        bool live = true;
-        if (ia == ib) live = lower_diag;
-        if (ib == JB) live = live && col_live;
-        const double upd = fma(-ci[ia], cc[ib], a[ia][ib]);
-        a[ia][ib] = live ? upd : a[ia][ib];
-      }
-    // publish the next pivot (its owner has just updated it)
-    const int jn = j + 1;
-    if (tr == (jn & 15) && tc == (jn & 15)) {
-      if (jr < 15) {
-        *piv = a[JB][JB];
-      } else if (JB + 1 < TT) {
-        *piv = a[JB + 1 < TT ? JB + 1 : JB][JB + 1 < TT ? JB + 1 : JB];
-      }
+    rank1_tiles<JB, JB, TT>(a, ci, cc, tr, tc, jr);
+    if (jr < 15) {
+      publish_column<JB>(a, next, rdg, jr + 1, tr, tc, w, k, st);
+    } else if (JB + 1 < TT) {
+      publish_column<JN>(a, next, rdg, 0, tr, tc, w, k, st);
     }
+    __syncthreads();  // column j + 1 published; column j no longer read
   }
 }
 
@@ -157,10 +183,8 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
                                                           int64_t k, int nb,
                                                           double* __restrict__ W,
                                                           DevState* __restrict__ st) {
-  __shared__ double col[NB];          // the current column of L
-  __shared__ double piv;              // the current pivot
+  __shared__ double colbuf[2 * NB];   // columns j and j + 1 of L
   __shared__ double Ld[NSB][SBB];     // diagonal 32 x 32 blocks of L, column-major
-  __shared__ double rowb[4][SB];      // per-wave row broadcast of the inversions
   __shared__ double rdg[NB];          // 1 / L(j,j)
   const int tid = threadIdx.x;
   const int tr = tid & 15, tc = tid >> 4;
@@ -179,16 +203,18 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
       }
       a[ia][ib] = v;
     }
-  if (tid == 0) piv = a[0][0];
   static_assert(TT == 8, "diagonal block tiling");
-  chol_block<0>(a, col, &piv, rdg, tr, tc, tid, k, st);
-  chol_block<1>(a, col, &piv, rdg, tr, tc, tid, k, st);
-  chol_block<2>(a, col, &piv, rdg, tr, tc, tid, k, st);
-  chol_block<3>(a, col, &piv, rdg, tr, tc, tid, k, st);
-  chol_block<4>(a, col, &piv, rdg, tr, tc, tid, k, st);
-  chol_block<5>(a, col, &piv, rdg, tr, tc, tid, k, st);
-  chol_block<6>(a, col, &piv, rdg, tr, tc, tid, k, st);
-  chol_block<7>(a, col, &piv, rdg, tr, tc, tid, k, st);
+  const int w = tid >> 6;
+  publish_column<0>(a, colbuf, rdg, 0, tr, tc, w, k, st);
+  __syncthreads();
+  chol_block<0>(a, colbuf, rdg, tr, tc, w, k, st);
+  chol_block<1>(a, colbuf, rdg, tr, tc, w, k, st);
+  chol_block<2>(a, colbuf, rdg, tr, tc, w, k, st);
+  chol_block<3>(a, colbuf, rdg, tr, tc, w, k, st);
+  chol_block<4>(a, colbuf, rdg, tr, tc, w, k, st);
+  chol_block<5>(a, colbuf, rdg, tr, tc, w, k, st);
+  chol_block<6>(a, colbuf, rdg, tr, tc, w, k, st);
+  chol_block<7>(a, colbuf, rdg, tr, tc, w, k, st);
   // L11 to global (lower part) and the diagonal blocks to LDS
 #pragma unroll
   for (int ia = 0; ia < TT; ++ia)
@@ -199,35 +225,30 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
       if ((i >> 5) == (c >> 5)) Ld[i >> 5][(c & 31) * SB + (i & 31)] = (i >= c) ? a[ia][ib] : 0.0;
     }
   __syncthreads();
-  // wave p inverts diagonal block p: lane (r, h) keeps W[r][16h .. 16h+15]
+  // Wave p inverts diagonal block p column by column: lane c solves
+  // L_pp y = e_c by forward substitution (y[i] = 0 for i < c falls out of
+  // the recursion); the upper lanes repeat the work and do not store.
   {
-    const int p = tid >> 6, lane = tid & 63, r = lane & 31, h = lane >> 5;
+    const int p = tid >> 6, c = tid & 31;
     const double* L = Ld[p];
-    double w[16];
+    const double* rd = rdg + SB * p;
+    double y[SB];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) w[c] = (r == 16 * h + c) ? 1.0 : 0.0;
-    for (int q = 0; q < SB; ++q) {
-      const double rq = rdg[SB * p + q];
-      if (r == q) {
+    for (int i = 0; i < SB; ++i) {
+      double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          w[c] = w[c] * rq;
-          rowb[p][16 * h + c] = w[c];
-        }
+      for (int q = 0; q + 1 < i; q += 2) {
+        s0 = fma(-L[q * SB + i], y[q], s0);
+        s1 = fma(-L[(q + 1) * SB + i], y[q + 1], s1);
       }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      if (r > q) {
-        const double lrq = L[q * SB + r];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) w[c] = fma(-lrq, rowb[p][16 * h + c], w[c]);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+      if (i & 1) s0 = fma(-L[(i - 1) * SB + i], y[i - 1], s0);
+      y[i] = (s0 + s1) * rd[i];
     }
-    double* Wp = W + p * SBB;
+    if ((tid & 63) < SB) {
+      double* Wc = W + p * SBB + c * SB;  // column c of Winv_p (column-major)
 #pragma unroll
-    for (int c = 0; c < 16; ++c) Wp[(16 * h + c) * SB + r] = w[c];
+      for (int i = 0; i < SB; ++i) Wc[i] = y[i];
+    }
   }
 }
 
@@ -314,7 +335,8 @@ __global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
 
 // ------------------------------------------------------------------------
 // 3. Trailing update C -= L L^T on the lower 128 x 128 tiles of the m x m
-//    trailing matrix; L is m x NB (column-major, ldl) in FP64 or FP32.
+//    trailing matrix; L is m x kdim (column-major, ldl) in FP64 or FP32,
+//    kdim a multiple of KC (one or two panels).
 //    Four waves, each a 64 x 64 quadrant (the strictly upper quadrant of a
 //    diagonal tile is skipped).  Operands are staged through double-buffered
 //    LDS in K-chunks of KC.
@@ -334,19 +356,20 @@ struct SyrkCfg<float> {
 
 constexpr int kPad = 4;
 
-// Tile sets of one trailing update: every lower tile, only the first tile
-// column (the next panel, updated ahead), or every lower tile but the first
-// column.
+// Tile sets of one trailing update: every lower tile, only the first nnext
+// tile columns (the next step's panels, updated ahead), or every lower tile
+// outside those columns.
 enum { kTilesAll = 0, kTilesNext = 1, kTilesRest = 2 };
 
-// Pipeline: the C tile is loaded into registers before the K loop (its
-// latency hides behind the MFMA work), operand chunks of KC columns go
-// global -> registers two chunks ahead and registers -> LDS one chunk
-// ahead (LDS double buffer).
+// Pipeline: operand chunks of KC columns go global -> registers two chunks
+// ahead and registers -> LDS one chunk ahead (LDS double buffer); the C tile
+// is read in the epilogue.  Registers and LDS are sized for two workgroups
+// per CU, so one workgroup's loads and stores overlap the other's MFMAs.
 template <typename T>
-__global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C, int64_t ld,
-                                                           const T* __restrict__ L, int64_t ldl,
-                                                           int64_t m, int tiles) {
+__global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict__ C, int64_t ld,
+                                                              const T* __restrict__ L, int64_t ldl,
+                                                              int64_t m, int kdim, int tiles,
+                                                              int nnext) {
   constexpr int KC = SyrkCfg<T>::KC;
   typedef typename SyrkCfg<T>::acc_t acc_t;
   constexpr int NLD = KC * kTS / 256;  // elements per thread per operand per chunk
@@ -358,13 +381,20 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
   const int t = xcd_contiguous(blockIdx.x, gridDim.x);
   int ti, tj;
   if (tiles == kTilesNext) {
-    ti = t;
-    tj = 0;
+    // tile column q holds tiles q .. mt-1; columns 0 .. nnext-1 in order
+    const int mt = (int)((m + kTS - 1) / kTS);
+    int q = 0, r = t;
+    while (q + 1 < nnext && r >= mt - q) {
+      r -= mt - q;
+      ++q;
+    }
+    ti = q + r;
+    tj = q;
   } else {
     tri_index(t, ti, tj);
     if (tiles == kTilesRest) {
-      ++ti;
-      ++tj;
+      ti += nnext;
+      tj += nnext;
     }
   }
   const int64_t row0 = (int64_t)ti * kTS, col0 = (int64_t)tj * kTS;
@@ -374,19 +404,12 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
   const bool active = !(ti == tj && wr < wc);
 
   acc_t acc[4][4];
-  // C tile prefetch (rows i, columns j of this lane's result registers)
-  double cv[4][4][4];
 #pragma unroll
   for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        acc[bj][bi][r] = 0;
-        const int64_t i = row0 + 64 * wr + 16 * bi + lr;
-        const int64_t j = col0 + 64 * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
-        cv[bj][bi][r] = (active && i < m && j < m && i >= j) ? C[j * ld + i] : 0.0;
-      }
+      for (int r = 0; r < 4; ++r) acc[bj][bi][r] = 0;
 
   T ra[NLD], rb[NLD];
   auto gload = [&](int kk) {
@@ -411,7 +434,7 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
     }
   };
 
-  constexpr int nch = NB / KC;
+  const int nch = kdim / KC;
   gload(0);
   sstore(0);
   if (nch > 1) gload(KC);
@@ -439,23 +462,35 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ C
     __syncthreads();
   }
   if (!active) return;
+  // C is read here, one 16-value batch per column block: with two
+  // workgroups per CU its latency overlaps the other workgroup's MFMA work
 #pragma unroll
-  for (int bj = 0; bj < 4; ++bj)
+  for (int bj = 0; bj < 4; ++bj) {
+    double cv[4][4];
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t i = row0 + 64 * wr + 16 * bi + lr;
         const int64_t j = col0 + 64 * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
-        if (i < m && j < m && i >= j) C[j * ld + i] = cv[bj][bi][r] - (double)acc[bj][bi][r];
+        cv[bi][r] = (i < m && j < m && i >= j) ? C[j * ld + i] : 0.0;
       }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = row0 + 64 * wr + 16 * bi + lr;
+        const int64_t j = col0 + 64 * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
+        if (i < m && j < m && i >= j) C[j * ld + i] = cv[bi][r] - (double)acc[bj][bi][r];
+      }
+  }
 }
 
 }  // namespace
 
 size_t cholesky_workspace_bytes(int64_t n, bd_precision_t prec) {
   size_t b = align_up(sizeof(double) * NB * NB, 256);  // four 32 x 32 inverses (NB*NB/4 used)
-  if (prec == BD_PREC_MIXED) b += 2 * align_up(sizeof(float) * (size_t)n * NB, 256);
+  if (prec == BD_PREC_MIXED) b += 2 * align_up(sizeof(float) * (size_t)n * kMaxStep, 256);
   return b;
 }
 
@@ -465,87 +500,127 @@ struct CholCtx {
   int64_t n, ld;
   double* A;
   double* W;
-  float* P32[2];  // FP32 copies of consecutive panels (MIXED), else null
+  // MIXED: FP32 copies of the panels of consecutive steps, n x kMaxStep each,
+  // indexed by global row (P[c * n + row]); null in FP64
+  float* P32[2];
+  int step;  // columns per step: 1 or 2 panels
   DevState* st;
 };
 
-hipError_t factor_panel(const CholCtx& c, hipStream_t s, int64_t k) {
-  const int nb = (int)((c.n - k < NB) ? (c.n - k) : NB);
-  BD_LAUNCH("potrf_diag", potrf_diag_kernel, dim3(1), dim3(256), 0, s, c.A, c.ld, k, nb, c.W,
+float* step_copy(const CholCtx& c, int64_t k0) {
+  return c.P32[0] ? c.P32[(k0 / c.step) & 1] : nullptr;
+}
+
+// Diagonal block and panel solve of the panel at column kp, which is panel
+// number (kp - k0) / NB of the step starting at k0.
+hipError_t factor_panel(const CholCtx& c, hipStream_t s, int64_t k0, int64_t kp) {
+  const int nb = (int)((c.n - kp < NB) ? (c.n - kp) : NB);
+  BD_LAUNCH("potrf_diag", potrf_diag_kernel, dim3(1), dim3(256), 0, s, c.A, c.ld, kp, nb, c.W,
             c.st);
-  const int64_t m = c.n - k - nb;
+  const int64_t m = c.n - kp - nb;
   if (m > 0) {  // then nb == NB: only the last panel can be narrower
-    float* P = c.P32[(k / NB) & 1];
-    BD_LAUNCH("panel_solve", panel_solve_kernel, dim3((unsigned)((m + kRB - 1) / kRB)), dim3(kPsThreads),
-              0, s, c.A, c.ld, k, nb, m, c.W, P, c.n);
+    float* P = step_copy(c, k0);
+    if (P) P += (kp - k0) * c.n + kp + NB;  // column kp - k0 of the step, row kp + NB
+    BD_LAUNCH("panel_solve", panel_solve_kernel, dim3((unsigned)((m + kRB - 1) / kRB)),
+              dim3(kPsThreads), 0, s, c.A, c.ld, kp, nb, m, c.W, P, c.n);
   }
   return hipGetLastError();
 }
 
-hipError_t trailing(const CholCtx& c, hipStream_t s, int64_t k, int tiles) {
-  const int64_t m = c.n - k - NB;
+// C -= L L^T on the trailing matrix from row/column r0 with the kdim columns
+// k0 .. k0 + kdim - 1 of L, restricted to a tile set.
+hipError_t trailing(const CholCtx& c, hipStream_t s, int64_t k0, int64_t r0, int kdim, int tiles,
+                    int nnext) {
+  const int64_t m = c.n - r0;
   const int64_t mt = (m + kTS - 1) / kTS;
-  unsigned nt = 0;
-  if (tiles == kTilesAll) nt = (unsigned)(mt * (mt + 1) / 2);
-  if (tiles == kTilesNext) nt = (unsigned)mt;
-  if (tiles == kTilesRest) nt = (unsigned)((mt - 1) * mt / 2);
-  if (nt == 0) return hipSuccess;
-  double* C = c.A + (k + NB) * c.ld + (k + NB);
-  const float* P = c.P32[(k / NB) & 1];
+  if (nnext > mt) nnext = (int)mt;
+  int64_t nt = 0;
+  if (tiles == kTilesAll) nt = mt * (mt + 1) / 2;
+  if (tiles == kTilesNext)
+    for (int q = 0; q < nnext; ++q) nt += mt - q;
+  if (tiles == kTilesRest) nt = (mt - nnext) * (mt - nnext + 1) / 2;
+  if (nt <= 0) return hipSuccess;
+  double* C = c.A + r0 * c.ld + r0;
+  const float* P = step_copy(c, k0);
   if (P) {
-    BD_LAUNCH("syrk_update_f32", syrk_update_kernel<float>, dim3(nt), dim3(256), 0, s, C, c.ld, P,
-              c.n, m, tiles);
+    BD_LAUNCH("syrk_update_f32", syrk_update_kernel<float>, dim3((unsigned)nt), dim3(256), 0, s, C,
+              c.ld, P + r0, c.n, m, kdim, tiles, nnext);
   } else {
-    BD_LAUNCH("syrk_update_f64", syrk_update_kernel<double>, dim3(nt), dim3(256), 0, s, C, c.ld,
-              (const double*)(c.A + k * c.ld + k + NB), c.ld, m, tiles);
+    BD_LAUNCH("syrk_update_f64", syrk_update_kernel<double>, dim3((unsigned)nt), dim3(256), 0, s,
+              C, c.ld, (const double*)(c.A + k0 * c.ld + r0), c.ld, m, kdim, tiles, nnext);
   }
   return hipGetLastError();
+}
+
+// The panels of the step starting at k0: each later panel first receives
+// the update by the step's earlier panels (one tile column), then is
+// factored.  Returns the step width.
+hipError_t factor_step(const CholCtx& c, hipStream_t s, int64_t k0, int64_t* width) {
+  int64_t kp = k0;
+  hipError_t e;
+  for (int p = 0; p < c.step / NB && kp < c.n; ++p, kp += NB) {
+    if (p > 0 && (e = trailing(c, s, k0, kp, (int)(kp - k0), kTilesNext, 1)) != hipSuccess)
+      return e;
+    if ((e = factor_panel(c, s, k0, kp)) != hipSuccess) return e;
+  }
+  *width = kp - k0;
+  return hipSuccess;
 }
 
 }  // namespace
 
-// Right-looking blocked factorisation with depth-1 lookahead: while the
-// main stream applies panel k to the trailing matrix (all but the next tile
-// column), the auxiliary stream updates the next tile column first, then
-// factors the next diagonal block and solves the next panel.  Events order
-// the two streams; with aux == nullptr everything runs on `s` in order.
+// Right-looking blocked factorisation in steps of one or two panels
+// (step = 2 applies two panels per pass over the trailing matrix, halving
+// its HBM traffic per flop), with depth-1 lookahead: while the main stream
+// applies step k0 to the trailing matrix (all but the next step's tile
+// columns), the auxiliary stream updates those tile columns first, then
+// factors the next step's panels.  Events order the two streams; with
+// aux == nullptr everything runs on `s` in order.
 hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[3], int64_t n, double* A,
-                           int64_t ld, bd_precision_t prec, void* ws, DevState* st) {
+                           int64_t ld, bd_precision_t prec, void* ws, DevState* st,
+                           int step_panels) {
   CholCtx c;
   c.n = n;
   c.ld = ld;
   c.A = A;
   c.st = st;
   c.W = static_cast<double*>(ws);
+  c.step = (step_panels == 2 ? 2 : 1) * NB;
   c.P32[0] = c.P32[1] = nullptr;
   if (prec == BD_PREC_MIXED) {
     char* p = static_cast<char*>(ws) + align_up(sizeof(double) * NB * NB, 256);
     c.P32[0] = reinterpret_cast<float*>(p);
-    c.P32[1] = reinterpret_cast<float*>(p + align_up(sizeof(float) * (size_t)n * NB, 256));
+    c.P32[1] = reinterpret_cast<float*>(p + align_up(sizeof(float) * (size_t)n * kMaxStep, 256));
   }
+  const int nnext = c.step / NB;
   hipError_t e;
+  int64_t w = 0;
   if (!aux) {
-    for (int64_t k = 0; k < n; k += NB) {
-      if ((e = factor_panel(c, s, k)) != hipSuccess) return e;
-      if (k + NB < n && (e = trailing(c, s, k, kTilesAll)) != hipSuccess) return e;
+    for (int64_t k = 0; k < n; k += w) {
+      if ((e = factor_step(c, s, k, &w)) != hipSuccess) return e;
+      if (k + w < n && (e = trailing(c, s, k, k + w, (int)w, kTilesAll, 0)) != hipSuccess) return e;
     }
     return hipGetLastError();
   }
   hipEvent_t ev_fork = ev[0], ev_panel = ev[1], ev_rest = ev[2];
   if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
   if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
-  if ((e = factor_panel(c, aux, 0)) != hipSuccess) return e;
+  if ((e = factor_step(c, aux, 0, &w)) != hipSuccess) return e;
   if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
-  for (int64_t k = 0; k + NB < n; k += NB) {
-    // main: panel k must be solved before it is applied
+  for (int64_t k = 0; k + w < n;) {
+    const int64_t r0 = k + w;
+    // main: step k must be factored before it is applied
     if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
-    // aux: the next tile column must have every earlier update
+    // aux: the next step's tile columns must have every earlier update
     if (k > 0 && (e = hipStreamWaitEvent(aux, ev_rest, 0)) != hipSuccess) return e;
-    if ((e = trailing(c, aux, k, kTilesNext)) != hipSuccess) return e;
-    if ((e = factor_panel(c, aux, k + NB)) != hipSuccess) return e;
+    if ((e = trailing(c, aux, k, r0, (int)w, kTilesNext, nnext)) != hipSuccess) return e;
+    int64_t wn = 0;
+    if ((e = factor_step(c, aux, r0, &wn)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
-    if ((e = trailing(c, s, k, kTilesRest)) != hipSuccess) return e;
+    if ((e = trailing(c, s, k, r0, (int)w, kTilesRest, nnext)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev_rest, s)) != hipSuccess) return e;
+    k = r0;
+    w = wn;
   }
   if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
   return hipGetLastError();

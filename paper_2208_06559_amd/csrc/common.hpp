@@ -30,6 +30,7 @@ constexpr int kWave = 64;
 // Cholesky blocking: trailing-update block (panel width) and MFMA tile.
 constexpr int kNB = 128;       // panel width
 constexpr int kTile = 128;     // trailing-update workgroup tile (square)
+constexpr int kMaxStep = 2 * kNB;  // widest factorisation step (two panels)
 
 // ---------------------------------------------------------------- launchers
 // rpy.hip
@@ -39,7 +40,8 @@ hipError_t launch_rpy_assemble(hipStream_t s, const bd_params_t& p, const double
 // cholesky.hip
 size_t cholesky_workspace_bytes(int64_t n, bd_precision_t prec);
 hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[3], int64_t n, double* A,
-                           int64_t ld, bd_precision_t prec, void* ws, DevState* st);
+                           int64_t ld, bd_precision_t prec, void* ws, DevState* st,
+                           int step_panels);
 
 // brownian.hip
 size_t brownian_workspace_bytes(int64_t n);

@@ -1,0 +1,103 @@
+// Runs the whole Cholesky launch sequence of cholesky.hip on the CPU (see
+// hip/hip_runtime.h) with exact-size buffers, so that AddressSanitizer
+// reports any out-of-bounds access of a kernel or of the host schedule.  In
+// FP64 it also checks the schedule itself from the launch arguments: every
+// lower 128 x 128 tile must receive the updates of columns 0 .. 128 J in
+// order, each exactly once, before its diagonal block is factored, and
+// every diagonal block is factored exactly once.
+// Usage: chol_emu n ld prec(0 fp64, 1 mixed) step_panels(1|2) lookahead(0|1)
+#include <map>
+#include <utility>
+
+#include "../../paper_2208_06559_amd/csrc/cholesky.hip"
+long g_emu_launches = 0;
+namespace bd {
+thread_local Profiler* g_prof = nullptr;
+void prof_mark_begin(hipStream_t, const char*) {}
+void prof_mark_end(hipStream_t) {}
+}  // namespace bd
+
+namespace {
+const double* g_A = nullptr;
+int64_t g_n = 0, g_ld = 0;
+std::map<std::pair<int64_t, int64_t>, int64_t> g_applied;  // tile -> columns applied
+std::map<int64_t, int> g_factored;                          // tile column -> times
+int g_errors = 0;
+
+void fail(const char* what, int64_t a, int64_t b, int64_t c) {
+  if (g_errors++ < 10) fprintf(stderr, "schedule error: %s (%lld, %lld, %lld)\n", what,
+                               (long long)a, (long long)b, (long long)c);
+}
+
+void observe(const void* kernel, dim3 grid, const int64_t* a, int nargs) {
+  using namespace bd;
+  if (kernel == (const void*)&syrk_update_kernel<double>) {
+    // (C, ld, L, ldl, m, kdim, tiles, nnext)
+    const int64_t coff = (a[0] - (int64_t)(uintptr_t)g_A) / 8, loff = (a[2] - (int64_t)(uintptr_t)g_A) / 8;
+    const int64_t r0 = coff / (g_ld + 1), k0 = (loff - r0) / g_ld;
+    const int64_t m = a[4], kdim = a[5], tiles = a[6], nnext = a[7];
+    if (coff != r0 * (g_ld + 1) || loff != k0 * g_ld + r0 || m != g_n - r0) fail("syrk args", r0, k0, m);
+    const int64_t mt = (m + kTS - 1) / kTS, nt = grid.x;
+    for (int64_t t = 0; t < nt; ++t) {
+      int64_t ti, tj;
+      if (tiles == kTilesNext) {
+        int64_t q = 0, r = t;
+        while (q + 1 < nnext && r >= mt - q) {
+          r -= mt - q;
+          ++q;
+        }
+        ti = q + r;
+        tj = q;
+      } else {
+        int rr, cc;
+        tri_index((int)t, rr, cc);
+        ti = rr;
+        tj = cc;
+        if (tiles == kTilesRest) {
+          ti += nnext;
+          tj += nnext;
+        }
+      }
+      if (ti >= mt || tj > ti) fail("tile outside region", ti, tj, mt);
+      const std::pair<int64_t, int64_t> key(r0 / kTS + ti, r0 / kTS + tj);
+      if (g_applied[key] != k0) fail("update out of order or repeated", key.first, key.second, k0);
+      g_applied[key] = k0 + kdim;
+    }
+  } else if (kernel == (const void*)&potrf_diag_kernel) {
+    // (A, ld, k, nb, W, st)
+    const int64_t kp = a[2], J = kp / NB;
+    for (int64_t I = J; I * NB < g_n; ++I)
+      if (g_applied[{I, J}] != kp) fail("factored before all updates", I, J, g_applied[{I, J}]);
+    if (g_factored[J]++) fail("diagonal block factored twice", J, kp, 0);
+  }
+}
+}  // namespace
+
+int main(int argc, char** argv) {
+  if (argc != 6) return 2;
+  const int64_t n = atoll(argv[1]), ld = atoll(argv[2]);
+  const int prec = atoi(argv[3]), sp = atoi(argv[4]), use_aux = atoi(argv[5]);
+  double* A = (double*)malloc(sizeof(double) * ((n - 1) * ld + n));
+  for (int64_t c = 0; c < n; ++c)
+    for (int64_t i = 0; i < n; ++i) A[c * ld + i] = (i == c) ? 1.0 + n : 0.1;
+  g_A = A;
+  g_n = n;
+  g_ld = ld;
+  if (prec == 0) g_emu_observer = observe;
+  const size_t wsb = bd::cholesky_workspace_bytes(n, (bd_precision_t)prec);
+  void* ws = malloc(wsb);
+  memset(ws, 0, wsb);
+  bd::DevState* st = (bd::DevState*)calloc(1, sizeof(bd::DevState));
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  const hipError_t e = bd::launch_cholesky(nullptr, use_aux ? (hipStream_t)0x1 : nullptr, ev, n, A,
+                                           ld, (bd_precision_t)prec, ws, st, sp);
+  if (prec == 0)
+    for (int64_t J = 0; J * bd::NB < n; ++J)
+      if (g_factored[J] != 1) fail("diagonal block not factored once", J, g_factored[J], 0);
+  printf("n=%lld ld=%lld prec=%d step_panels=%d lookahead=%d: status %d, %ld launches, %d schedule errors\n",
+         (long long)n, (long long)ld, prec, sp, use_aux, e, g_emu_launches, g_errors);
+  free(A);
+  free(ws);
+  free(st);
+  return (e != hipSuccess || g_errors) ? 1 : 0;
+}

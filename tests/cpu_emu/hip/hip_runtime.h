@@ -1,0 +1,75 @@
+// Host-only stand-in for the HIP runtime, for checking the memory accesses
+// of the library's kernels on the CPU under AddressSanitizer: a launch runs
+// every thread of every workgroup to completion, one after another.
+// Barriers, cross-lane reads and matrix-core instructions become no-ops or
+// scalar stand-ins, so values are meaningless; addresses are exact because
+// no kernel computes an address from data.
+#pragma once
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <algorithm>
+#include <type_traits>
+using std::sqrt; using std::fabs; using std::fma; using std::isinf; using std::isnan;
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __shared__ static
+#define __launch_bounds__(...)
+struct dim3 {
+  unsigned x, y, z;
+  constexpr dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+inline dim3 threadIdx, blockIdx, blockDim, gridDim;
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+typedef struct ihipStream_t* hipStream_t;
+typedef struct ihipEvent_t* hipEvent_t;
+inline hipError_t hipGetLastError() { return hipSuccess; }
+inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+inline hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
+inline void __syncthreads() {}
+inline void __threadfence() {}
+#define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) ((c) + (a) * (b))
+#define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) ((c) + (a) * (b))
+#define __builtin_amdgcn_readlane(v, l) (v)
+#define __builtin_amdgcn_rsq(d) (1.0 / std::sqrt(d))
+#define __builtin_amdgcn_fence(...) ((void)0)
+#define __builtin_amdgcn_wave_barrier() ((void)0)
+template <typename T> inline T __shfl_xor(T v, int, int = 64) { return v; }
+extern long g_emu_launches;
+// Optional observer of every launch: kernel address, grid, and the
+// arguments as 64-bit values (pointers as addresses, integers as values,
+// anything else as 0).
+typedef void (*emu_observer_t)(const void* kernel, dim3 grid, const int64_t* args, int nargs);
+inline emu_observer_t g_emu_observer = nullptr;
+template <typename T>
+inline int64_t emu_arg(T v) {
+  if constexpr (std::is_pointer_v<T>) return (int64_t)(uintptr_t)v;
+  else if constexpr (std::is_integral_v<T> || std::is_enum_v<T>) return (int64_t)v;
+  else return 0;
+}
+template <typename K, typename... Args>
+inline void emu_launch(K kernel, dim3 grid, dim3 block, Args... args) {
+  ++g_emu_launches;
+  if (g_emu_observer) {
+    const int64_t a[] = {emu_arg(args)..., 0};
+    g_emu_observer((const void*)kernel, grid, a, (int)sizeof...(Args));
+  }
+  gridDim = grid;
+  blockDim = block;
+  for (unsigned bz = 0; bz < grid.z; ++bz)
+    for (unsigned by = 0; by < grid.y; ++by)
+      for (unsigned bx = 0; bx < grid.x; ++bx)
+        for (unsigned tz = 0; tz < block.z; ++tz)
+          for (unsigned ty = 0; ty < block.y; ++ty)
+            for (unsigned tx = 0; tx < block.x; ++tx) {
+              blockIdx = dim3(bx, by, bz);
+              threadIdx = dim3(tx, ty, tz);
+              kernel(args...);
+            }
+}
+#define hipLaunchKernelGGL(kernel, grid, block, shmem, stream, ...) emu_launch(kernel, dim3(grid), dim3(block), __VA_ARGS__)

@@ -105,6 +105,41 @@ def test_cholesky_mixed_residual(h, N, seed):
     assert np.all(np.diag(L) > 0)
 
 
+@pytest.mark.parametrize("step_panels", ["1", "2"])
+@pytest.mark.parametrize("lookahead", ["0", "1"])
+@pytest.mark.parametrize("prec", [B.PREC_FP64, B.PREC_MIXED])
+def test_cholesky_schedules(monkeypatch, step_panels, lookahead, prec):
+    """Every factorisation schedule (one or two panels per trailing pass,
+    with or without the lookahead stream) on a ragged n spanning several
+    steps: FP64 to the rounding level of the oracle's factor, MIXED through
+    its residual bound."""
+    monkeypatch.setenv("BDRPY_STEP_PANELS", step_panels)
+    monkeypatch.setenv("BDRPY_LOOKAHEAD", lookahead)
+    hh = B.Handle(0)
+    try:
+        N = 367  # n = 1101: eight full panels and a 77-column tail
+        pg, po = _params(N)
+        x = I.random_walk(N, seed=5)
+        n = 3 * N
+        Dref = o.rpy_assemble(po, x, o.FILL_FULL)
+        ld = n + 1
+        A = _colmajor_buffer(np.tril(Dref), ld)
+        hh.cholesky(A, n, ld, prec)
+        assert hh.info()["status"] == B.OK
+        L = np.tril(_from_buffer(A, n))
+        if prec == B.PREC_FP64:
+            Lref, info = o.cholesky(Dref)
+            assert info == 0
+            Lref = np.tril(Lref)  # the oracle leaves the strict upper part as given
+            err = np.abs(L - Lref).max() / np.abs(Lref).max()
+            assert err <= 1e-13, err
+        else:
+            res = np.linalg.norm(L @ L.T - Dref) / np.linalg.norm(Dref)
+            assert res <= 1e-6, res
+    finally:
+        hh.close()
+
+
 def test_cholesky_not_spd_reports_column(h):
     n = 300
     M = np.eye(n)
