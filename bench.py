@@ -37,11 +37,14 @@ def chol_flops(n: int) -> float:
     return n**3 / 3.0 + n**2 / 2.0 + n / 6.0
 
 
-def syrk_launches(n: int, nb: int = 128, step_panels: int = 2) -> list[tuple[float, float, int]]:
+def syrk_launches(n: int, nb: int = 128, step_panels: int = 2,
+                  lookahead: bool = True) -> list[tuple]:
     """Every trailing-update launch of one factorisation in the library's
     schedule (steps of `step_panels` panels with lookahead): per launch
-    (flops, lower elements updated, operand rows, kdim) with flops = 2 per
-    multiply-add over the lower elements of the tiles it updates."""
+    (flops, lower elements updated, operand rows, kdim, kind) with flops = 2
+    per multiply-add over the lower elements of the tiles it updates; kind
+    "next" for the columns of the next step (the lookahead chain, kernel
+    syrk_next_*), "bulk" for the rest (kernel syrk_update_*)."""
     step = step_panels * nb
     out = []
 
@@ -64,7 +67,8 @@ def syrk_launches(n: int, nb: int = 128, step_panels: int = 2) -> list[tuple[flo
             nt = mt * (mt + 1) // 2
             elems, rows = m * (m + 1) // 2, m
         if nt > 0:
-            out.append((2.0 * elems * kdim, float(elems), rows, kdim))
+            out.append((2.0 * elems * kdim, float(elems), rows, kdim,
+                        "next" if tiles == "next" else "bulk"))
 
     def factor_step(k0):
         kp, p = k0, 0
@@ -75,6 +79,14 @@ def syrk_launches(n: int, nb: int = 128, step_panels: int = 2) -> list[tuple[flo
             kp += nb
         return kp - k0
 
+    if not lookahead:
+        k = 0
+        while k < n:
+            w = factor_step(k)
+            if k + w < n:
+                trailing(k + w, w, "all", 0)
+            k += w
+        return out
     w, k = factor_step(0), 0
     while k + w < n:
         r0 = k + w
@@ -85,13 +97,14 @@ def syrk_launches(n: int, nb: int = 128, step_panels: int = 2) -> list[tuple[flo
     return out
 
 
-def syrk_per_launch(n: int, esize: int) -> tuple[float, float, int]:
-    """Average algorithmic flops and HBM bytes per trailing-update launch,
-    and the launch count, of one factorisation.  Bytes: each updated lower
-    element of C read and written once in FP64 (16 B) plus each operand row
-    of L read once (kdim values of `esize` bytes)."""
+def syrk_per_launch(n: int, esize: int, kind: str = "bulk") -> tuple[float, float, int]:
+    """Average algorithmic flops and HBM bytes per trailing-update launch of
+    one kind, and the launch count, of one factorisation.  Bytes: each
+    updated lower element of C read and written once in FP64 (16 B) plus
+    each operand row of L read once (kdim values of `esize` bytes)."""
     sp = 1 if os.environ.get("BDRPY_STEP_PANELS", "").startswith("1") else 2
-    ls = syrk_launches(n, step_panels=sp)
+    la = not os.environ.get("BDRPY_LOOKAHEAD", "").startswith("0")
+    ls = [x for x in syrk_launches(n, step_panels=sp, lookahead=la) if x[4] == kind]
     fl = sum(x[0] for x in ls)
     by = sum(16.0 * x[1] + x[2] * x[3] * esize for x in ls)
     return fl / len(ls), by / len(ls), len(ls)

@@ -334,12 +334,12 @@ __global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
 }
 
 // ------------------------------------------------------------------------
-// 3. Trailing update C -= L L^T on the lower 128 x 128 tiles of the m x m
-//    trailing matrix; L is m x kdim (column-major, ldl) in FP64 or FP32,
-//    kdim a multiple of KC (one or two panels).
-//    Four waves, each a 64 x 64 quadrant (the strictly upper quadrant of a
-//    diagonal tile is skipped).  Operands are staged through double-buffered
-//    LDS in K-chunks of KC.
+// 3. Trailing update C -= L L^T on the lower TS x TS tiles (TS = 128, or 64
+//    for the columns on the lookahead chain) of the m x m trailing matrix; L
+//    is m x kdim (column-major, ldl) in FP64 or FP32, kdim a multiple of KC
+//    (one or two panels).  Four waves, each a TS/2 x TS/2 quadrant (the
+//    strictly upper quadrant of a diagonal tile is skipped).  Operands are
+//    staged through double-buffered LDS in K-chunks of KC.
 // ------------------------------------------------------------------------
 template <typename T>
 struct SyrkCfg;
@@ -365,16 +365,19 @@ enum { kTilesAll = 0, kTilesNext = 1, kTilesRest = 2 };
 // ahead and registers -> LDS one chunk ahead (LDS double buffer); the C tile
 // is read in the epilogue.  Registers and LDS are sized for two workgroups
 // per CU, so one workgroup's loads and stores overlap the other's MFMAs.
-template <typename T>
+template <typename T, int TS>
 __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict__ C, int64_t ld,
                                                               const T* __restrict__ L, int64_t ldl,
                                                               int64_t m, int kdim, int tiles,
                                                               int nnext) {
   constexpr int KC = SyrkCfg<T>::KC;
   typedef typename SyrkCfg<T>::acc_t acc_t;
-  constexpr int NLD = KC * kTS / 256;  // elements per thread per operand per chunk
-  __shared__ T As[2][KC][kTS + kPad];  // row side
-  __shared__ T Bs[2][KC][kTS + kPad];  // column side
+  constexpr int WT = TS / 2;           // each wave owns a WT x WT quadrant
+  constexpr int NBK = WT / 16;         // 16 x 16 MFMA blocks per quadrant side
+  constexpr int NLD = KC * TS / 256;   // elements per thread per operand per chunk
+  static_assert(TS == 64 || TS == 128, "tile size");
+  __shared__ T As[2][KC][TS + kPad];  // row side
+  __shared__ T Bs[2][KC][TS + kPad];  // column side
 
   // XCD x receives workgroups x, x+8, ...: cnt(x) = base + (x < rem) of them;
   // the q-th of them takes tile x*base + min(x, rem) + q (a bijection).
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
   int ti, tj;
   if (tiles == kTilesNext) {
     // tile column q holds tiles q .. mt-1; columns 0 .. nnext-1 in order
-    const int mt = (int)((m + kTS - 1) / kTS);
+    const int mt = (int)((m + TS - 1) / TS);
     int q = 0, r = t;
     while (q + 1 < nnext && r >= mt - q) {
       r -= mt - q;
@@ -397,17 +400,17 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
       tj += nnext;
     }
   }
-  const int64_t row0 = (int64_t)ti * kTS, col0 = (int64_t)tj * kTS;
+  const int64_t row0 = (int64_t)ti * TS, col0 = (int64_t)tj * TS;
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   const int wr = w >> 1, wc = w & 1;
   const bool active = !(ti == tj && wr < wc);
 
-  acc_t acc[4][4];
+  acc_t acc[NBK][NBK];
 #pragma unroll
-  for (int bj = 0; bj < 4; ++bj)
+  for (int bj = 0; bj < NBK; ++bj)
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+    for (int bi = 0; bi < NBK; ++bi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[bj][bi][r] = 0;
 
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
 #pragma unroll
     for (int q = 0; q < NLD; ++q) {
       const int e = tid + 256 * q;
-      const int kc = e / kTS, r = e % kTS;
+      const int kc = e / TS, r = e % TS;
       // rows past m are clamped (their products only reach masked outputs)
       const int64_t ia = (row0 + r < m) ? row0 + r : m - 1;
       const int64_t ib = (col0 + r < m) ? col0 + r : m - 1;
@@ -428,7 +431,7 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
 #pragma unroll
     for (int q = 0; q < NLD; ++q) {
       const int e = tid + 256 * q;
-      const int kc = e / kTS, r = e % kTS;
+      const int kc = e / TS, r = e % TS;
       As[buf][kc][r] = ra[q];
       Bs[buf][kc][r] = rb[q];
     }
@@ -444,15 +447,15 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
     if (active) {
 #pragma unroll
       for (int kq = 0; kq < KC / 4; ++kq) {
-        T af[4], bf[4];
+        T af[NBK], bf[NBK];
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj) af[bj] = Bs[buf][4 * kq + lk][64 * wc + 16 * bj + lr];
+        for (int bj = 0; bj < NBK; ++bj) af[bj] = Bs[buf][4 * kq + lk][WT * wc + 16 * bj + lr];
 #pragma unroll
-        for (int bi = 0; bi < 4; ++bi) bf[bi] = As[buf][4 * kq + lk][64 * wr + 16 * bi + lr];
+        for (int bi = 0; bi < NBK; ++bi) bf[bi] = As[buf][4 * kq + lk][WT * wr + 16 * bi + lr];
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
+        for (int bj = 0; bj < NBK; ++bj)
 #pragma unroll
-          for (int bi = 0; bi < 4; ++bi) acc[bj][bi] = mfma(af[bj], bf[bi], acc[bj][bi]);
+          for (int bi = 0; bi < NBK; ++bi) acc[bj][bi] = mfma(af[bj], bf[bi], acc[bj][bi]);
       }
     }
     if (ch + 1 < nch) {
@@ -465,22 +468,22 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
   // C is read here, one 16-value batch per column block: with two
   // workgroups per CU its latency overlaps the other workgroup's MFMA work
 #pragma unroll
-  for (int bj = 0; bj < 4; ++bj) {
-    double cv[4][4];
+  for (int bj = 0; bj < NBK; ++bj) {
+    double cv[NBK][4];
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+    for (int bi = 0; bi < NBK; ++bi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = row0 + 64 * wr + 16 * bi + lr;
-        const int64_t j = col0 + 64 * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
+        const int64_t i = row0 + WT * wr + 16 * bi + lr;
+        const int64_t j = col0 + WT * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
         cv[bi][r] = (i < m && j < m && i >= j) ? C[j * ld + i] : 0.0;
       }
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
+    for (int bi = 0; bi < NBK; ++bi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = row0 + 64 * wr + 16 * bi + lr;
-        const int64_t j = col0 + 64 * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
+        const int64_t i = row0 + WT * wr + 16 * bi + lr;
+        const int64_t j = col0 + WT * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
         if (i < m && j < m && i >= j) C[j * ld + i] = cv[bi][r] - (double)acc[bj][bi][r];
       }
   }
@@ -531,8 +534,12 @@ hipError_t factor_panel(const CholCtx& c, hipStream_t s, int64_t k0, int64_t kp)
 // k0 .. k0 + kdim - 1 of L, restricted to a tile set.
 hipError_t trailing(const CholCtx& c, hipStream_t s, int64_t k0, int64_t r0, int kdim, int tiles,
                     int nnext) {
+  // The next-step columns lie on the lookahead chain: 64 x 64 tiles spread
+  // them over four times as many CUs; the bulk update keeps 128 x 128 tiles.
+  const int ts = (tiles == kTilesNext) ? kTS / 2 : kTS;
+  nnext *= NB / ts;  // in tiles
   const int64_t m = c.n - r0;
-  const int64_t mt = (m + kTS - 1) / kTS;
+  const int64_t mt = (m + ts - 1) / ts;
   if (nnext > mt) nnext = (int)mt;
   int64_t nt = 0;
   if (tiles == kTilesAll) nt = mt * (mt + 1) / 2;
@@ -542,12 +549,20 @@ hipError_t trailing(const CholCtx& c, hipStream_t s, int64_t k0, int64_t r0, int
   if (nt <= 0) return hipSuccess;
   double* C = c.A + r0 * c.ld + r0;
   const float* P = step_copy(c, k0);
-  if (P) {
-    BD_LAUNCH("syrk_update_f32", syrk_update_kernel<float>, dim3((unsigned)nt), dim3(256), 0, s, C,
+  const double* L64 = c.A + k0 * c.ld + r0;
+  const dim3 grid((unsigned)nt);
+  if (P && ts == kTS) {
+    BD_LAUNCH("syrk_update_f32", (syrk_update_kernel<float, kTS>), grid, dim3(256), 0, s, C, c.ld,
+              P + r0, c.n, m, kdim, tiles, nnext);
+  } else if (P) {
+    BD_LAUNCH("syrk_next_f32", (syrk_update_kernel<float, kTS / 2>), grid, dim3(256), 0, s, C,
               c.ld, P + r0, c.n, m, kdim, tiles, nnext);
+  } else if (ts == kTS) {
+    BD_LAUNCH("syrk_update_f64", (syrk_update_kernel<double, kTS>), grid, dim3(256), 0, s, C,
+              c.ld, L64, c.ld, m, kdim, tiles, nnext);
   } else {
-    BD_LAUNCH("syrk_update_f64", syrk_update_kernel<double>, dim3((unsigned)nt), dim3(256), 0, s,
-              C, c.ld, (const double*)(c.A + k0 * c.ld + r0), c.ld, m, kdim, tiles, nnext);
+    BD_LAUNCH("syrk_next_f64", (syrk_update_kernel<double, kTS / 2>), grid, dim3(256), 0, s, C,
+              c.ld, L64, c.ld, m, kdim, tiles, nnext);
   }
   return hipGetLastError();
 }

@@ -3,7 +3,8 @@
 // reports any out-of-bounds access of a kernel or of the host schedule.  In
 // FP64 it also checks the schedule itself from the launch arguments: every
 // lower 128 x 128 tile must receive the updates of columns 0 .. 128 J in
-// order, each exactly once, before its diagonal block is factored, and
+// order, each exactly once, before its diagonal block is factored (tracked
+// on 64 x 64 sub-tiles, the finest tile a launch uses), and
 // every diagonal block is factored exactly once.
 // Usage: chol_emu n ld prec(0 fp64, 1 mixed) step_panels(1|2) lookahead(0|1)
 #include <map>
@@ -31,13 +32,16 @@ void fail(const char* what, int64_t a, int64_t b, int64_t c) {
 
 void observe(const void* kernel, dim3 grid, const int64_t* a, int nargs) {
   using namespace bd;
-  if (kernel == (const void*)&syrk_update_kernel<double>) {
-    // (C, ld, L, ldl, m, kdim, tiles, nnext)
+  int64_t ts = 0;
+  if (kernel == (const void*)&syrk_update_kernel<double, kTS>) ts = kTS;
+  if (kernel == (const void*)&syrk_update_kernel<double, kTS / 2>) ts = kTS / 2;
+  if (ts) {
+    // (C, ld, L, ldl, m, kdim, tiles, nnext): tile size ts, nnext in tiles
     const int64_t coff = (a[0] - (int64_t)(uintptr_t)g_A) / 8, loff = (a[2] - (int64_t)(uintptr_t)g_A) / 8;
     const int64_t r0 = coff / (g_ld + 1), k0 = (loff - r0) / g_ld;
     const int64_t m = a[4], kdim = a[5], tiles = a[6], nnext = a[7];
     if (coff != r0 * (g_ld + 1) || loff != k0 * g_ld + r0 || m != g_n - r0) fail("syrk args", r0, k0, m);
-    const int64_t mt = (m + kTS - 1) / kTS, nt = grid.x;
+    const int64_t mt = (m + ts - 1) / ts, nt = grid.x;
     for (int64_t t = 0; t < nt; ++t) {
       int64_t ti, tj;
       if (tiles == kTilesNext) {
@@ -59,15 +63,23 @@ void observe(const void* kernel, dim3 grid, const int64_t* a, int nargs) {
         }
       }
       if (ti >= mt || tj > ti) fail("tile outside region", ti, tj, mt);
-      const std::pair<int64_t, int64_t> key(r0 / kTS + ti, r0 / kTS + tj);
-      if (g_applied[key] != k0) fail("update out of order or repeated", key.first, key.second, k0);
-      g_applied[key] = k0 + kdim;
+      // bookkeeping in 64 x 64 units
+      const int64_t f = ts / 64;
+      for (int64_t u = 0; u < f; ++u)
+        for (int64_t v = 0; v < f; ++v) {
+          const int64_t I = (r0 + ti * ts) / 64 + u, J = (r0 + tj * ts) / 64 + v;
+          if (I < J || I * 64 >= g_n) continue;
+          const std::pair<int64_t, int64_t> key(I, J);
+          if (g_applied[key] != k0) fail("update out of order or repeated", I, J, k0);
+          g_applied[key] = k0 + kdim;
+        }
     }
   } else if (kernel == (const void*)&potrf_diag_kernel) {
     // (A, ld, k, nb, W, st)
     const int64_t kp = a[2], J = kp / NB;
-    for (int64_t I = J; I * NB < g_n; ++I)
-      if (g_applied[{I, J}] != kp) fail("factored before all updates", I, J, g_applied[{I, J}]);
+    for (int64_t I = kp / 64; I * 64 < g_n; ++I)
+      for (int64_t Jc = kp / 64; Jc < kp / 64 + NB / 64 && Jc <= I && Jc * 64 < g_n; ++Jc)
+        if (g_applied[{I, Jc}] != kp) fail("factored before all updates", I, Jc, g_applied[{I, Jc}]);
     if (g_factored[J]++) fail("diagonal block factored twice", J, kp, 0);
   }
 }
