@@ -96,49 +96,90 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Column j = 16 IB + jn is held by the 16 threads tc == jn, which are 16
-// consecutive lanes of wave jn / 4; the pivot A(j,j) sits in the lane with
-// tr == tc == jn.  That wave reads the pivot across lanes (no LDS round
-// trip), the owners scale the column by 1/sqrt(pivot) and write it to the
-// LDS column buffer.  IB is a template parameter so that every register
-// index is a compile-time constant.
+__device__ __forceinline__ double shfl_f64(double v, int src_lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, (int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Columns j0 .. j0 + 3 (j0 = 16 IB + 4 q) are held by the threads
+// tc = 4q .. 4q + 3, which are the four 16-lane groups g = tc & 3 of wave q
+// (lane = tr + 16 g); their rows tr + 16 ia sit in a[ia][IB].  With every
+// update by columns < j0 applied, that wave factors the four columns on its
+// own: per column, the pivot is read across lanes, the column's group
+// scales it by 1/sqrt(pivot), and the groups of the later columns apply it
+// (its values fetched across lanes by row, the multipliers L(j0+g, j) by
+// lane reads).  The four columns then go to the LDS buffer colq[4][NB].
+// IB is a template parameter so that every register index is a constant.
 template <int IB>
-__device__ __forceinline__ void publish_column(double (&a)[TT][TT], double* __restrict__ colv,
-                                               double* __restrict__ rdg, int jn, int tr, int tc,
-                                               int w, int64_t k, DevState* __restrict__ st) {
-  if (w != (jn >> 2)) return;  // wave-uniform
-  const int j = 16 * IB + jn;
-  const double d = readlane_f64(a[IB][IB], 16 * (jn & 3) + jn);
-  if (tc != jn) return;
-  if (tr == jn && !(d > 0.0) && st->potrf_info == 0) {
-    st->potrf_info = k + j + 1;
-    st->status = BD_ERR_NOT_SPD;
+__device__ __forceinline__ void factor_quad(double (&a)[TT][TT], double* __restrict__ colq,
+                                            double* __restrict__ rdg, int q, int tr, int tc,
+                                            int64_t k, DevState* __restrict__ st) {
+  const int g = tc & 3;
+  const int j0 = 16 * IB + 4 * q;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int j = j0 + c;
+    const double d = readlane_f64(a[IB][IB], (4 * q + c) + 16 * c);  // A(j, j)
+    if (g == c && tr == 4 * q + c && !(d > 0.0) && st->potrf_info == 0) {
+      st->potrf_info = k + j + 1;
+      st->status = BD_ERR_NOT_SPD;
+    }
+    const double rs = rsqrt_refined(d);  // NaN for a non-positive pivot
+    if (g == c) {
+#pragma unroll
+      for (int ia = IB; ia < TT; ++ia) {
+        const int i = tr + 16 * ia;
+        if (i == j) {
+          a[ia][IB] = d * rs;
+          rdg[j] = rs;  // 1 / L(j,j), used by the diagonal-block inversion
+        } else if (i > j) {
+          a[ia][IB] *= rs;
+        }
+      }
+    }
+    if (c < 3) {
+      double lv[TT];  // L(tr + 16 ia, j) in every lane
+#pragma unroll
+      for (int ia = IB; ia < TT; ++ia) lv[ia] = shfl_f64(a[ia][IB], tr + 16 * c);
+      // L(j0 + g, j) for the groups g > c: row j0 + g of column j
+      const double s1 = readlane_f64(a[IB][IB], (4 * q + c + 1) + 16 * c);
+      const double s2 = (c + 2 < 4) ? readlane_f64(a[IB][IB], (4 * q + c + 2) + 16 * c) : 0.0;
+      const double s3 = (c + 3 < 4) ? readlane_f64(a[IB][IB], (4 * q + c + 3) + 16 * c) : 0.0;
+      const double sv = (g == c + 1) ? s1 : ((g == c + 2) ? s2 : s3);
+      if (g > c) {
+#pragma unroll
+        for (int ia = IB; ia < TT; ++ia) a[ia][IB] = fma(-lv[ia], sv, a[ia][IB]);
+      }
+    }
   }
-  const double rs = rsqrt_refined(d);  // NaN for a non-positive pivot
 #pragma unroll
   for (int ia = IB; ia < TT; ++ia) {
     const int i = tr + 16 * ia;
-    if (i == j) {
-      a[ia][IB] = d * rs;
-      colv[i] = a[ia][IB];
-      rdg[j] = rs;  // 1 / L(j,j), used by the diagonal-block inversion
-    } else if (i > j) {
-      a[ia][IB] *= rs;
-      colv[i] = a[ia][IB];
-    }
+    if (i >= j0 + g) colq[g * NB + i] = a[ia][IB];
   }
 }
 
-// Rank-1 update by column j = 16 JB + jr (values ci, cc read from the
-// column buffer) of the tile columns IB0 <= ib < IB1.  Only tiles ib >= JB,
-// ia >= ib can hold live elements: for ia < ib every row is above every
-// column, for ia > ib every row is below; within ia == ib only tr >= tc;
-// and columns c > j need checking only at ib == JB.
+// Rank-4 update by the published columns j0 .. j0 + 3 (j0 = 16 JB + 4 q) of
+// the tile columns IB0 <= ib < IB1.  Only tiles ib >= JB, ia >= ib can hold
+// live elements: for ia < ib every row is above every column, for ia > ib
+// every row is below; within ia == ib only tr >= tc; and at ib == JB only
+// the columns past j0 + 3.
 template <int JB, int IB0, int IB1>
-__device__ __forceinline__ void rank1_tiles(double (&a)[TT][TT], const double (&ci)[TT],
-                                            const double (&cc)[TT], int tr, int tc, int jr) {
+__device__ __forceinline__ void rank4_tiles(double (&a)[TT][TT], const double* __restrict__ colq,
+                                            int q, int tr, int tc) {
+  if (IB0 >= IB1) return;
   const bool lower_diag = tr >= tc;
-  const bool col_live = tc > jr;  // column tc + 16 JB is past j
+  const bool col_live = tc > 4 * q + 3;
+  double ci[4][TT], cc[4][TT];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+#pragma unroll
+    for (int ia = IB0; ia < TT; ++ia) ci[u][ia] = colq[u * NB + tr + 16 * ia];
+#pragma unroll
+    for (int ib = IB0; ib < IB1; ++ib) cc[u][ib] = colq[u * NB + tc + 16 * ib];
+  }
 #pragma unroll
   for (int ib = IB0; ib < IB1; ++ib)
 #pragma unroll
@@ -146,36 +187,39 @@ __device__ __forceinline__ void rank1_tiles(double (&a)[TT][TT], const double (&
       bool live = true;
       if (ia == ib) live = lower_diag;
       if (ib == JB) live = live && col_live;
-      const double upd = fma(-ci[ia], cc[ib], a[ia][ib]);
+      double upd = a[ia][ib];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) upd = fma(-ci[u][ia], cc[u][ib], upd);
       a[ia][ib] = live ? upd : a[ia][ib];
     }
 }
 
-// Columns 16 JB .. 16 JB + 15: with column j published in colbuf[j & 1],
-// every thread applies it to its live trailing elements, then the owners of
-// column j + 1 (just brought up to date) publish it into the other buffer;
-// one barrier per column.
+// Columns 16 JB .. 16 JB + 15 in four quads.  Quad number qi = 4 JB + q is
+// published in colq buffer qi & 1.  Each thread first updates the tile
+// column that holds the next quad, whose owning wave then factors and
+// publishes it into the other buffer while the remaining tiles are
+// updated; one barrier per quad.
 template <int JB>
-__device__ __forceinline__ void chol_block(double (&a)[TT][TT], double* __restrict__ colbuf,
+__device__ __forceinline__ void chol_block(double (&a)[TT][TT], double* __restrict__ colq,
                                            double* __restrict__ rdg, int tr, int tc, int w,
                                            int64_t k, DevState* __restrict__ st) {
-  constexpr int JN = (JB + 1 < TT) ? JB + 1 : JB;  // tile column of 16 (JB + 1)
-  for (int jr = 0; jr < 16; ++jr) {
-    const int j = 16 * JB + jr;
-    const double* col = colbuf + (j & 1) * NB;
-    double* next = colbuf + ((j + 1) & 1) * NB;
-    double ci[TT], cc[TT];
+  constexpr int JN = (JB + 1 < TT) ? JB + 1 : JB;  // tile column of the quad after this block
 #pragma unroll
-    for (int ia = JB; ia < TT; ++ia) ci[ia] = col[tr + 16 * ia];
-#pragma unroll
-    for (int ib = JB; ib < TT; ++ib) cc[ib] = col[tc + 16 * ib];
-    rank1_tiles<JB, JB, TT>(a, ci, cc, tr, tc, jr);
-    if (jr < 15) {
-      publish_column<JB>(a, next, rdg, jr + 1, tr, tc, w, k, st);
+  for (int q = 0; q < 4; ++q) {
+    const int qi = 4 * JB + q;
+    const double* cur = colq + (qi & 1) * 4 * NB;
+    double* nxt = colq + ((qi + 1) & 1) * 4 * NB;
+    if (q < 3) {
+      rank4_tiles<JB, JB, JB + 1>(a, cur, q, tr, tc);
+      if (w == q + 1) factor_quad<JB>(a, nxt, rdg, q + 1, tr, tc, k, st);
+      rank4_tiles<JB, JB + 1, TT>(a, cur, q, tr, tc);
     } else if (JB + 1 < TT) {
-      publish_column<JN>(a, next, rdg, 0, tr, tc, w, k, st);
+      // no column of tile column JB is past the last quad of the block
+      rank4_tiles<JB, JN, JN + 1>(a, cur, q, tr, tc);
+      if (w == 0) factor_quad<JN>(a, nxt, rdg, 0, tr, tc, k, st);
+      rank4_tiles<JB, JN + 1, TT>(a, cur, q, tr, tc);
     }
-    __syncthreads();  // column j + 1 published; column j no longer read
+    __syncthreads();  // next quad published; this quad no longer read
   }
 }
 
@@ -183,7 +227,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
                                                           int64_t k, int nb,
                                                           double* __restrict__ W,
                                                           DevState* __restrict__ st) {
-  __shared__ double colbuf[2 * NB];   // columns j and j + 1 of L
+  __shared__ double colq[2 * 4 * NB]; // two buffers of four columns of L
   __shared__ double Ld[NSB][SBB];     // diagonal 32 x 32 blocks of L, column-major
   __shared__ double rdg[NB];          // 1 / L(j,j)
   const int tid = threadIdx.x;
@@ -205,16 +249,16 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
     }
   static_assert(TT == 8, "diagonal block tiling");
   const int w = tid >> 6;
-  publish_column<0>(a, colbuf, rdg, 0, tr, tc, w, k, st);
+  if (w == 0) factor_quad<0>(a, colq, rdg, 0, tr, tc, k, st);
   __syncthreads();
-  chol_block<0>(a, colbuf, rdg, tr, tc, w, k, st);
-  chol_block<1>(a, colbuf, rdg, tr, tc, w, k, st);
-  chol_block<2>(a, colbuf, rdg, tr, tc, w, k, st);
-  chol_block<3>(a, colbuf, rdg, tr, tc, w, k, st);
-  chol_block<4>(a, colbuf, rdg, tr, tc, w, k, st);
-  chol_block<5>(a, colbuf, rdg, tr, tc, w, k, st);
-  chol_block<6>(a, colbuf, rdg, tr, tc, w, k, st);
-  chol_block<7>(a, colbuf, rdg, tr, tc, w, k, st);
+  chol_block<0>(a, colq, rdg, tr, tc, w, k, st);
+  chol_block<1>(a, colq, rdg, tr, tc, w, k, st);
+  chol_block<2>(a, colq, rdg, tr, tc, w, k, st);
+  chol_block<3>(a, colq, rdg, tr, tc, w, k, st);
+  chol_block<4>(a, colq, rdg, tr, tc, w, k, st);
+  chol_block<5>(a, colq, rdg, tr, tc, w, k, st);
+  chol_block<6>(a, colq, rdg, tr, tc, w, k, st);
+  chol_block<7>(a, colq, rdg, tr, tc, w, k, st);
   // L11 to global (lower part) and the diagonal blocks to LDS
 #pragma unroll
   for (int ia = 0; ia < TT; ++ia)

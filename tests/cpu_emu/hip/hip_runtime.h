@@ -36,6 +36,7 @@ inline void __threadfence() {}
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) ((c) + (a) * (b))
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) ((c) + (a) * (b))
 #define __builtin_amdgcn_readlane(v, l) (v)
+#define __builtin_amdgcn_ds_bpermute(addr, v) (v)
 #define __builtin_amdgcn_rsq(d) (1.0 / std::sqrt(d))
 #define __builtin_amdgcn_fence(...) ((void)0)
 #define __builtin_amdgcn_wave_barrier() ((void)0)
