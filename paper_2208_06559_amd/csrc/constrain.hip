@@ -6,16 +6,18 @@
 // through the full diffusion tensor of Eqs. 7-9).  Then x^{t+dt} = x* + dt r.
 //
 // Inexact Newton from T = 0; each Newton correction J delta = -g is solved by
-// GMRES (modified Gram-Schmidt, Givens) right-preconditioned with the
+// GMRES (classical Gram-Schmidt with one re-orthogonalisation, Givens
+// rotations) right-preconditioned with the
 // tridiagonal part of J, J_kl = -2 dt Q_k . G_kl u_l, G_kl = D_{k+1,l+1} -
 // D_{k+1,l} - D_{k,l+1} + D_{k,l}.  Every product with D is matrix-free.
 //
 // Device work is split in two kernels that the host launches alternately:
 //   dmatvec     r = D f over all bead pairs, one workgroup per 16 beads i
 //               (no atomics, fixed reduction order);
-//   controller  one workgroup of 512 threads: advances the Newton/GMRES state machine by one matrix-vector
-//               product (residual check, band Jacobian, Arnoldi step, PCR
-//               tridiagonal solve in LDS), then writes the next f.
+//   controller  one workgroup of 512 threads: advances the Newton/GMRES
+//               state machine by one matrix-vector product (residual check,
+//               band Jacobian, Arnoldi step, cyclic-reduction tridiagonal
+//               solve in LDS), then writes the next f.
 // Once the iteration has finished both kernels return immediately.
 #include "common.hpp"
 #include "profile.hpp"
@@ -42,7 +44,7 @@ struct NewtonCtl {
 };
 
 struct Bufs {
-  double *u, *Qs, *Q, *Gd, *Gp, *Gm, *T, *lo, *di, *up, *rhs, *z, *f, *r, *V, *H, *cs, *sn, *s, *y;
+  double *u, *Qs, *Q, *Gd, *Gp, *Gm, *T, *lo, *di, *up, *f, *r, *V, *H, *cs, *sn, *s;
   NewtonCtl* ctl;
 };
 
@@ -66,8 +68,6 @@ Bufs carve(void* ws, int N) {
   b.lo = take(M);
   b.di = take(M);
   b.up = take(M);
-  b.rhs = take(M);
-  b.z = take(M);
   b.f = take(3 * (size_t)N);
   b.r = take(3 * (size_t)N);
   b.V = take((size_t)(kKmax + 1) * M);
@@ -75,7 +75,6 @@ Bufs carve(void* ws, int N) {
   b.cs = take(kKmax);
   b.sn = take(kKmax);
   b.s = take(kKmax + 1);
-  b.y = take(kKmax);
   b.ctl = reinterpret_cast<NewtonCtl*>(take(8));
   return b;
 }
@@ -341,114 +340,156 @@ __device__ void block_sum8(double v[8], double (*red8)[8]) {
   __syncthreads();
 }
 
-// Parallel cyclic reduction (Hockney) for the tridiagonal system
-// (lo, di, up) x = v, M <= kMaxRods, in LDS; result to out (global).
-__device__ void pcr_solve(const double* __restrict__ lo, const double* __restrict__ di,
-                          const double* __restrict__ up, const double* __restrict__ v,
-                          double* __restrict__ out, int M, double* pa, double* pb, double* pc,
-                          double* pd) {
-  constexpr int R = kMaxRods / kCtlThreads;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < M; i += kCtlThreads) {
-    pa[i] = lo[i];
-    pb[i] = di[i];
-    pc[i] = up[i];
-    pd[i] = v[i];
-  }
-  __syncthreads();
-  for (int s = 1; s < M; s <<= 1) {
-    double na[R], nb[R], nc[R], nd[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int i = tid + q * kCtlThreads;
-      if (i < M) {
-        double bb = pb[i], dd = pd[i], aa = 0.0, cc = 0.0;
-        if (i - s >= 0) {
-          const double al = -pa[i] / pb[i - s];
-          aa = al * pa[i - s];
-          bb += al * pc[i - s];
-          dd += al * pd[i - s];
-        }
-        if (i + s < M) {
-          const double ga = -pc[i] / pb[i + s];
-          cc = ga * pc[i + s];
-          bb += ga * pa[i + s];
-          dd += ga * pd[i + s];
-        }
-        na[q] = aa; nb[q] = bb; nc[q] = cc; nd[q] = dd;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int i = tid + q * kCtlThreads;
-      if (i < M) {
-        pa[i] = na[q]; pb[i] = nb[q]; pc[i] = nc[q]; pd[i] = nd[q];
-      }
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < M; i += kCtlThreads) out[i] = pd[i] / pb[i];
-  __syncthreads();
+// 1/x from the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp_refined(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
 }
 
-// f_i = z_i u_i - z_{i-1} u_{i-1}
-__device__ void rod_forces(const double* __restrict__ z, const double* __restrict__ u,
+// Cyclic reduction (odd-even elimination) for the tridiagonal system
+// (pa, pb, pc) x = pd of M <= kMaxRods unknowns, all in LDS and filled by
+// the caller; the solution is left in pd.  Forward levels s = 1, 2, 4, ...
+// eliminate the couplings of rows i = 2s m + 2s - 1 to rows i -+ s (rows
+// read and rows written at one level are disjoint, so one barrier per
+// level); backward levels solve rows i = 2s m + s - 1 from rows i -+ s.
+// The first row's sub-diagonal and the last row's super-diagonal are zero.
+// Every LDS read is unconditional (clamped index, contribution selected)
+// so that a level costs one LDS round trip.
+constexpr int kR = kMaxRods / kCtlThreads;  // unknowns per thread (k = tid + kCtlThreads q)
+
+__device__ __forceinline__ int lp(int i) { return i + (i >> 5); }  // padded LDS index
+constexpr int kPadRods = kMaxRods + kMaxRods / 32;
+
+__device__ void cr_solve(int M, double* pa, double* pb, double* pc, double* pd) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  int s = 1;
+  for (; 2 * s - 1 < M; s <<= 1) {
+    for (int i = 2 * s - 1 + 2 * s * tid; i < M; i += 2 * s * kCtlThreads) {
+      const bool right = i + s < M;
+      const int ir = right ? i + s : i;
+      const int p = lp(i), pl = lp(i - s), pr = lp(ir);
+      const double ai = pa[p], bi = pb[p], ci = pc[p], di = pd[p];
+      const double al_ = pa[pl], bl_ = pb[pl], cl_ = pc[pl], dl_ = pd[pl];
+      const double ar_ = pa[pr], br_ = pb[pr], cr_ = pc[pr], dr_ = pd[pr];
+      const double al = -ai * rcp_refined(bl_);
+      const double ga = right ? -ci * rcp_refined(br_) : 0.0;
+      pa[p] = al * al_;
+      pb[p] = bi + al * cl_ + ga * ar_;
+      pc[p] = ga * cr_;
+      pd[p] = di + al * dl_ + ga * dr_;
+    }
+    __syncthreads();
+  }
+  for (; s >= 1; s >>= 1) {
+    for (int i = s - 1 + 2 * s * tid; i < M; i += 2 * s * kCtlThreads) {
+      const bool left = i - s >= 0, right = i + s < M;
+      const int p = lp(i);
+      const double xl = pd[lp(left ? i - s : i)], xr = pd[lp(right ? i + s : i)];
+      double t = pd[p];
+      if (left) t -= pa[p] * xl;
+      if (right) t -= pc[p] * xr;
+      pd[p] = t * rcp_refined(pb[p]);
+    }
+    __syncthreads();
+  }
+}
+
+// f_i = z_i u_i - z_{i-1} u_{i-1} with z in LDS (z_{-1} = z_{N-1} = 0).  The
+// bead loop has a fixed trip count and every load a valid (clamped) index, so
+// all loads of u issue together.
+__device__ void rod_forces(const double* z, const double* __restrict__ u,
                            double* __restrict__ f, int N) {
   const int M = N - 1;
-  for (int i = threadIdx.x; i < N; i += kCtlThreads) {
+#pragma unroll
+  for (int q = 0; q <= kR; ++q) {
+    if (q % 3 == 0) __builtin_amdgcn_sched_barrier(0);  // loads in groups of three beads
+    const int i = threadIdx.x + q * kCtlThreads;
+    const int ic = (i < M) ? i : M - 1, im = (i > 0 && i - 1 < M) ? i - 1 : 0;
+    double ui[3], um[3];
 #pragma unroll
     for (int al = 0; al < 3; ++al) {
-      double v = 0.0;
-      if (i < M) v += z[i] * u[3 * i + al];
-      if (i > 0) v -= z[i - 1] * u[3 * (i - 1) + al];
-      f[3 * i + al] = v;
+      ui[al] = u[3 * ic + al];
+      um[al] = u[3 * im + al];
+    }
+    if (i < N) {
+      const double zi = (i < M) ? z[lp(i)] : 0.0, zm = (i > 0) ? z[lp(i - 1)] : 0.0;
+#pragma unroll
+      for (int al = 0; al < 3; ++al) f[3 * i + al] = zi * ui[al] - zm * um[al];
     }
   }
 }
 
+// The controller keeps the serial parts of GMRES (rotations, the small
+// triangular solve) in LDS and each thread's share of the Krylov vector in
+// registers (unknowns k = tid + kCtlThreads q): global memory is touched only
+// by batches of independent loads and by the stores of the next state.
 __global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
     Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, double dt,
     double bl, double tol, int maxit, DevState* __restrict__ st) {
-  __shared__ double pa[kMaxRods], pb[kMaxRods], pc[kMaxRods], pd[kMaxRods];
+  __shared__ double pa[kPadRods], pb[kPadRods], pc[kPadRods], pd[kPadRods];
   __shared__ double red[kCtlThreads / 64];
   __shared__ double red8[kCtlThreads / 64][8];
   __shared__ double hcur[kKmax + 1], hsum[kKmax + 1];
+  __shared__ double cs_s[kKmax], sn_s[kKmax], s_s[kKmax + 1], y_s[kKmax];
   __shared__ int sh_flag;
-  if (st->done) return;
   const int tid = threadIdx.x;
   const int M = N - 1;
   const int64_t n3 = 3 * (int64_t)N;
   NewtonCtl* ctl = b.ctl;
-  const int phase = ctl->phase;
+  // state: independent loads, one round trip
+  const int done = st->done;
+  const int phase = ctl->phase, j = ctl->j, newton_it = ctl->newton_it;
+  const double beta_c = ctl->beta, eta = ctl->eta;
+  if (done) return;
   if (phase == PH_RESID) {
     double err = 0.0, res = 0.0, g2 = 0.0;
-    for (int k = tid; k < M; k += kCtlThreads) {
-      double q[3];
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      if (q % 2 == 0) __builtin_amdgcn_sched_barrier(0);  // loads in groups of two rods
+      const int k = tid + q * kCtlThreads;
+      const int kc = (k < M) ? k : M - 1;  // valid index: loads issue together
+      double qv[3], gd[3], gp[3], gm[3];
 #pragma unroll
       for (int al = 0; al < 3; ++al) {
-        q[al] = b.Qs[3 * k + al] + dt * (b.r[3 * (k + 1) + al] - b.r[3 * k + al]);
-        b.Q[3 * k + al] = q[al];
+        qv[al] = b.Qs[3 * kc + al] + dt * (b.r[3 * (kc + 1) + al] - b.r[3 * kc + al]);
+        gd[al] = b.Gd[3 * kc + al];
+        gp[al] = b.Gp[3 * kc + al];
+        gm[al] = b.Gm[3 * kc + al];
       }
-      const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
-      const double e = fabs(sqrt(q2) / bl - 1.0);
-      const double g = q2 - bl * bl;
-      err = nanmax(err, e);
-      res = nanmax(res, fabs(g));
-      g2 += g * g;
-      b.rhs[k] = -g;
+      if (k < M) {
+#pragma unroll
+        for (int al = 0; al < 3; ++al) b.Q[3 * k + al] = qv[al];
+        const double q2 = qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2];
+        const double e = fabs(sqrt(q2) / bl - 1.0);
+        const double g = q2 - bl * bl;
+        err = nanmax(err, e);
+        res = nanmax(res, fabs(g));
+        g2 += g * g;
+        pd[lp(k)] = -g;
+        const double di = -2.0 * dt * (qv[0] * gd[0] + qv[1] * gd[1] + qv[2] * gd[2]);
+        const double up = (k + 1 < M) ? -2.0 * dt * (qv[0] * gp[0] + qv[1] * gp[1] + qv[2] * gp[2]) : 0.0;
+        const double lo = (k > 0) ? -2.0 * dt * (qv[0] * gm[0] + qv[1] * gm[1] + qv[2] * gm[2]) : 0.0;
+        b.di[k] = di;
+        b.up[k] = up;
+        b.lo[k] = lo;
+        pa[lp(k)] = lo;
+        pb[lp(k)] = di;
+        pc[lp(k)] = up;
+      }
     }
     err = block_max(err, red);
     res = block_max(res, red);
     g2 = block_sum(g2, red);
-    const int it = ctl->newton_it;
-    if (err <= tol || it >= maxit || !(err == err) || isinf(err)) {
+    if (err <= tol || newton_it >= maxit || !(err == err) || isinf(err)) {
       for (int64_t e = tid; e < n3; e += kCtlThreads) xs[e] += dt * b.r[e];
       if (T_out)
         for (int k = tid; k < M; k += kCtlThreads) T_out[k] = b.T[k];
       if (tid == 0) {
         if (st->status == BD_OK) st->status = (err <= tol) ? BD_OK : BD_ERR_NO_CONVERGE;
-        st->newton_iters = it;
+        st->newton_iters = newton_it;
         st->krylov_iters = ctl->kry;
         st->max_rod_err = err;
         st->last_newton_res = res;
@@ -456,49 +497,62 @@ __global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
       }
       return;
     }
-    for (int k = tid; k < M; k += kCtlThreads) {
-      const double* q = b.Q + 3 * k;
-      const double* gd = b.Gd + 3 * k;
-      const double* gp = b.Gp + 3 * k;
-      const double* gm = b.Gm + 3 * k;
-      b.di[k] = -2.0 * dt * (q[0] * gd[0] + q[1] * gd[1] + q[2] * gd[2]);
-      b.up[k] = (k + 1 < M) ? -2.0 * dt * (q[0] * gp[0] + q[1] * gp[1] + q[2] * gp[2]) : 0.0;
-      b.lo[k] = (k > 0) ? -2.0 * dt * (q[0] * gm[0] + q[1] * gm[1] + q[2] * gm[2]) : 0.0;
-    }
     // inexact-Newton forcing term: balance the quadratic term of g against
     // the linear-solve error, never tighter than the final tolerance needs
     const double grms = sqrt(g2 / (double)M) / (bl * bl);
-    double eta = 0.25 * grms;
+    double eta_n = 0.25 * grms;
     const double floor_eta = 0.5 * tol / grms;
-    if (eta < floor_eta) eta = floor_eta;
-    if (eta > 0.1) eta = 0.1;
+    if (eta_n < floor_eta) eta_n = floor_eta;
+    if (eta_n > 0.1) eta_n = 0.1;
     const double beta = sqrt(g2);
-    for (int k = tid; k < M; k += kCtlThreads) b.V[k] = b.rhs[k] / beta;
-    __syncthreads();
+    const double rb = 1.0 / beta;
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      const int k = tid + q * kCtlThreads;
+      if (k < M) {
+        const double v0 = pd[lp(k)] * rb;
+        b.V[k] = v0;
+        pd[lp(k)] = v0;
+      }
+    }
     if (tid == 0) {
       b.s[0] = beta;
       ctl->phase = PH_KRYLOV;
       ctl->j = 0;
       ctl->beta = beta;
-      ctl->eta = eta;
+      ctl->eta = eta_n;
     }
-    pcr_solve(b.lo, b.di, b.up, b.V, b.z, M, pa, pb, pc, pd);
-    rod_forces(b.z, b.u, b.f, N);
+    cr_solve(M, pa, pb, pc, pd);
+    rod_forces(pd, b.u, b.f, N);
     return;
   }
 
-  // PH_KRYLOV: r = D f(z_j); w = J z_j into V[j+1]
-  const int j = ctl->j;
-  const double beta = ctl->beta, eta = ctl->eta;
-  double* w = b.V + (int64_t)(j + 1) * M;
-  for (int k = tid; k < M; k += kCtlThreads) {
-    const double* q = b.Q + 3 * k;
-    const double d0 = b.r[3 * (k + 1)] - b.r[3 * k];
-    const double d1 = b.r[3 * (k + 1) + 1] - b.r[3 * k + 1];
-    const double d2 = b.r[3 * (k + 1) + 2] - b.r[3 * k + 2];
-    w[k] = 2.0 * dt * (q[0] * d0 + q[1] * d1 + q[2] * d2);
+  // PH_KRYLOV: r = D f(z_j); w = J z_j becomes V[j+1]
+  const double beta = beta_c;
+  // small GMRES state to LDS, and the tridiagonal for the preconditioner
+  if (tid < j) {
+    cs_s[tid] = b.cs[tid];
+    sn_s[tid] = b.sn[tid];
   }
-  __syncthreads();
+  if (tid <= j) s_s[tid] = b.s[tid];
+  double wv[kR];
+#pragma unroll
+  for (int q = 0; q < kR; ++q) {
+    const int k = tid + q * kCtlThreads;
+    const int kc = (k < M) ? k : M - 1;  // valid index: loads issue together
+    const double* qk = b.Q + 3 * kc;
+    const double d0 = b.r[3 * (kc + 1)] - b.r[3 * kc];
+    const double d1 = b.r[3 * (kc + 1) + 1] - b.r[3 * kc + 1];
+    const double d2 = b.r[3 * (kc + 1) + 2] - b.r[3 * kc + 2];
+    const double v = 2.0 * dt * (qk[0] * d0 + qk[1] * d1 + qk[2] * d2);
+    const double lo = b.lo[kc], di = b.di[kc], up = b.up[kc];
+    wv[q] = (k < M) ? v : 0.0;
+    if (k < M) {
+      pa[lp(k)] = lo;
+      pb[lp(k)] = di;
+      pc[lp(k)] = up;
+    }
+  }
   // Classical Gram-Schmidt with one re-orthogonalisation: each pass forms
   // every projection h_i = <w, v_i> (block reductions of 8 at a time), then
   // w -= sum_i h_i v_i.
@@ -509,11 +563,21 @@ __global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
       double pr[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) pr[u] = 0.0;
-      for (int k = tid; k < M; k += kCtlThreads) {
-        const double wk = w[k];
+      // two halves of four vectors: each half's loads issue together
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (i0 + u <= j) pr[u] += wk * b.V[(int64_t)(i0 + u) * M + k];
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int q = 0; q < kR; ++q) {
+          const int k = tid + q * kCtlThreads;
+          const int kc = (k < M) ? k : M - 1;  // wv is 0 past M
+#pragma unroll
+          for (int u = 4 * h; u < 4 * h + 4; ++u) {
+            double v = 0.0;  // wave-uniform condition: the load issues without a wait
+            if (i0 + u <= j) v = b.V[(i0 + u) * M + kc];
+            pr[u] += wv[q] * v;
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
       block_sum8(pr, red8);
       if (tid < 8 && i0 + tid <= j) {
@@ -522,68 +586,160 @@ __global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
       }
       __syncthreads();
     }
-    for (int k = tid; k < M; k += kCtlThreads) {
-      double acc = 0.0;
-      for (int i = 0; i <= j; ++i) acc += hcur[i] * b.V[(int64_t)i * M + k];
-      w[k] -= acc;
-    }
-    __syncthreads();
-  }
-  if (tid <= j) b.H[tid * kKmax + j] = hsum[tid];
-  double part = 0.0;
-  for (int k = tid; k < M; k += kCtlThreads) part += w[k] * w[k];
-  const double hn = sqrt(block_sum(part, red));
-  if (hn > 0.0)
-    for (int k = tid; k < M; k += kCtlThreads) w[k] /= hn;
-  __syncthreads();
-  if (tid == 0) {
-    double* H = b.H;
-    H[(j + 1) * kKmax + j] = hn;
-    for (int i = 0; i < j; ++i) {
-      const double a0 = H[i * kKmax + j], a1 = H[(i + 1) * kKmax + j];
-      H[i * kKmax + j] = b.cs[i] * a0 + b.sn[i] * a1;
-      H[(i + 1) * kKmax + j] = -b.sn[i] * a0 + b.cs[i] * a1;
-    }
-    const double a0 = H[j * kKmax + j], a1 = H[(j + 1) * kKmax + j];
-    const double den = sqrt(a0 * a0 + a1 * a1);
-    b.cs[j] = (den > 0.0) ? a0 / den : 1.0;
-    b.sn[j] = (den > 0.0) ? a1 / den : 0.0;
-    H[j * kKmax + j] = den;
-    H[(j + 1) * kKmax + j] = 0.0;
-    b.s[j + 1] = -b.sn[j] * b.s[j];
-    b.s[j] = b.cs[j] * b.s[j];
-    ctl->kry += 1;
-    const int stop = (fabs(b.s[j + 1]) <= eta * beta) || (hn == 0.0) || (j + 1 == kKmax);
-    sh_flag = stop;
-    if (stop) {
-      const int kk = j + 1;
-      for (int i = kk - 1; i >= 0; --i) {
-        double t = b.s[i];
-        for (int c = i + 1; c < kk; ++c) t -= H[i * kKmax + c] * b.y[c];
-        b.y[i] = t / H[i * kKmax + i];
+    // w -= sum_i h_i v_i, vectors in batches of 8 so that their loads issue
+    // together
+    double acc[kR];
+#pragma unroll
+    for (int q = 0; q < kR; ++q) acc[q] = 0.0;
+    for (int i0 = 0; i0 <= j; i0 += 8) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int q = 0; q < kR; ++q) {
+          const int k = tid + q * kCtlThreads;
+          const int kc = (k < M) ? k : M - 1;
+#pragma unroll
+          for (int u = 4 * h; u < 4 * h + 4; ++u) {
+            double v = 0.0, hv = 0.0;
+            if (i0 + u <= j) {
+              v = b.V[(i0 + u) * M + kc];
+              hv = hcur[i0 + u];
+            }
+            acc[q] += hv * v;
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
+#pragma unroll
+    for (int q = 0; q < kR; ++q)
+      if (tid + q * kCtlThreads < M) wv[q] -= acc[q];  // w stays 0 past M
+  }
+  double part = 0.0;
+#pragma unroll
+  for (int q = 0; q < kR; ++q) part += wv[q] * wv[q];
+  const double hn = sqrt(block_sum(part, red));
+  const double rhn = (hn > 0.0) ? 1.0 / hn : 0.0;
+#pragma unroll
+  for (int q = 0; q < kR; ++q) {
+    const int k = tid + q * kCtlThreads;
+    if (hn > 0.0) wv[q] *= rhn;
+    if (k < M) b.V[(j + 1) * M + k] = wv[q];
+  }
+  if (tid == 0) {
+    // rotate the new Hessenberg column (hsum, hn) by the previous Givens
+    // rotations and form the next one; column j of R goes to H
+    double hcol_next = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a0 = hsum[i], a1 = hsum[i + 1];
+      hsum[i] = cs_s[i] * a0 + sn_s[i] * a1;
+      hsum[i + 1] = -sn_s[i] * a0 + cs_s[i] * a1;
+    }
+    const double a0 = hsum[j], a1 = hcol_next;
+    const double den = sqrt(a0 * a0 + a1 * a1);
+    const double csj = (den > 0.0) ? a0 / den : 1.0;
+    const double snj = (den > 0.0) ? a1 / den : 0.0;
+    hsum[j] = den;
+    cs_s[j] = csj;
+    sn_s[j] = snj;
+    s_s[j + 1] = -snj * s_s[j];
+    s_s[j] = csj * s_s[j];
+    b.cs[j] = csj;
+    b.sn[j] = snj;
+    b.s[j] = s_s[j];
+    b.s[j + 1] = s_s[j + 1];
+    for (int i = 0; i <= j; ++i) b.H[i * kKmax + j] = hsum[i];
+    ctl->kry += 1;
+    sh_flag = (fabs(s_s[j + 1]) <= eta * beta) || (hn == 0.0) || (j + 1 == kKmax);
   }
   __syncthreads();
   if (sh_flag) {
+    // y = R^-1 s on the j+1 columns; R's earlier columns come from H
     const int kk = j + 1;
-    for (int k = tid; k < M; k += kCtlThreads) {
-      double acc = 0.0;
-      for (int i = 0; i < kk; ++i) acc += b.y[i] * b.V[(int64_t)i * M + k];
-      b.rhs[k] = acc;
+    double* Rs = pc;  // kk x kk upper triangle, row-major (pc is free here)
+    for (int e0 = 0; e0 < kk * kk; e0 += kCtlThreads) {
+      const int e = e0 + tid;
+      const int ec = (e < kk * kk) ? e : 0;
+      const int i = ec / kk, c = ec % kk;
+      const double h = b.H[i * kKmax + c];  // any i, c < kKmax is a valid index
+      if (e < kk * kk) Rs[e] = (c < j && i <= c) ? h : 0.0;
     }
     __syncthreads();
-    pcr_solve(b.lo, b.di, b.up, b.rhs, b.z, M, pa, pb, pc, pd);
-    for (int k = tid; k < M; k += kCtlThreads) b.T[k] += b.z[k];
-    __syncthreads();
-    rod_forces(b.T, b.u, b.f, N);
     if (tid == 0) {
-      ctl->newton_it += 1;
+      for (int i = 0; i <= j; ++i) Rs[i * kk + j] = hsum[i];
+      for (int i = kk - 1; i >= 0; --i) {
+        double t = s_s[i];
+        for (int c = i + 1; c < kk; ++c) t -= Rs[i * kk + c] * y_s[c];
+        y_s[i] = t / Rs[i * kk + i];
+      }
+    }
+    __syncthreads();
+    // Newton correction: T += P^-1 (V y), with P the tridiagonal part of J
+    double acc[kR];
+#pragma unroll
+    for (int q = 0; q < kR; ++q) acc[q] = 0.0;
+    for (int i0 = 0; i0 < kk; i0 += 8) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int q = 0; q < kR; ++q) {
+          const int k = tid + q * kCtlThreads;
+          const int kc = (k < M) ? k : M - 1;
+#pragma unroll
+          for (int u = 4 * h; u < 4 * h + 4; ++u) {
+            double v = 0.0, yv = 0.0;
+            if (i0 + u < kk) {
+              v = b.V[(i0 + u) * M + kc];
+              yv = y_s[i0 + u];
+            }
+            acc[q] += yv * v;
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      const int k = tid + q * kCtlThreads;
+      const int kc = (k < M) ? k : M - 1;
+      const double lo = b.lo[kc], di = b.di[kc], up = b.up[kc];
+      if (k < M) {
+        pa[lp(k)] = lo;
+        pb[lp(k)] = di;
+        pc[lp(k)] = up;
+        pd[lp(k)] = acc[q];
+      }
+    }
+    double told[kR];  // loaded before the solve so that its latency is hidden
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      const int k = tid + q * kCtlThreads;
+      told[q] = b.T[(k < M) ? k : M - 1];
+    }
+    cr_solve(M, pa, pb, pc, pd);
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      const int k = tid + q * kCtlThreads;
+      if (k < M) {
+        const double t = told[q] + pd[lp(k)];
+        b.T[k] = t;
+        pa[lp(k)] = t;
+      }
+    }
+    __syncthreads();
+    rod_forces(pa, b.u, b.f, N);
+    if (tid == 0) {
+      ctl->newton_it = newton_it + 1;
       ctl->phase = PH_RESID;
     }
   } else {
-    pcr_solve(b.lo, b.di, b.up, w, b.z, M, pa, pb, pc, pd);
-    rod_forces(b.z, b.u, b.f, N);
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      const int k = tid + q * kCtlThreads;
+      if (k < M) pd[lp(k)] = wv[q];
+    }
+    cr_solve(M, pa, pb, pc, pd);
+    rod_forces(pd, b.u, b.f, N);
     if (tid == 0) ctl->j = j + 1;
   }
 }

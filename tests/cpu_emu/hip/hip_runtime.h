@@ -31,6 +31,13 @@ typedef struct ihipEvent_t* hipEvent_t;
 inline hipError_t hipGetLastError() { return hipSuccess; }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 inline hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
+enum hipMemcpyKind { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice, hipMemcpyDeviceToHost,
+                     hipMemcpyDeviceToDevice, hipMemcpyDefault };
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) {
+  memcpy(d, s, n);
+  return hipSuccess;
+}
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 inline void __syncthreads() {}
 inline void __threadfence() {}
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) ((c) + (a) * (b))
@@ -38,8 +45,10 @@ inline void __threadfence() {}
 #define __builtin_amdgcn_readlane(v, l) (v)
 #define __builtin_amdgcn_ds_bpermute(addr, v) (v)
 #define __builtin_amdgcn_rsq(d) (1.0 / std::sqrt(d))
+#define __builtin_amdgcn_rcp(d) (1.0 / (d))
 #define __builtin_amdgcn_fence(...) ((void)0)
 #define __builtin_amdgcn_wave_barrier() ((void)0)
+#define __builtin_amdgcn_sched_barrier(m) ((void)0)
 template <typename T> inline T __shfl_xor(T v, int, int = 64) { return v; }
 extern long g_emu_launches;
 // Optional observer of every launch: kernel address, grid, and the
@@ -47,6 +56,9 @@ extern long g_emu_launches;
 // anything else as 0).
 typedef void (*emu_observer_t)(const void* kernel, dim3 grid, const int64_t* args, int nargs);
 inline emu_observer_t g_emu_observer = nullptr;
+// A kernel whose threads are not run (only observed), e.g. one too large to
+// emulate at a given size.
+inline const void* g_emu_skip = nullptr;
 template <typename T>
 inline int64_t emu_arg(T v) {
   if constexpr (std::is_pointer_v<T>) return (int64_t)(uintptr_t)v;
@@ -60,6 +72,7 @@ inline void emu_launch(K kernel, dim3 grid, dim3 block, Args... args) {
     const int64_t a[] = {emu_arg(args)..., 0};
     g_emu_observer((const void*)kernel, grid, a, (int)sizeof...(Args));
   }
+  if ((const void*)kernel == g_emu_skip) return;
   gridDim = grid;
   blockDim = block;
   for (unsigned bz = 0; bz < grid.z; ++bz)

@@ -1,5 +1,6 @@
-"""Memory-access check of the Cholesky kernels and their launch schedule on
-the CPU: cholesky.hip is compiled as host C++ against a stand-in HIP runtime
+"""Memory-access check of the Cholesky and tension-solve kernels and their
+launch schedules on the CPU: the sources are compiled as host C++ against a
+stand-in HIP runtime
 that runs every thread of every launch in turn, under AddressSanitizer, with
 buffers of exactly the sizes the library documents (matrix (n-1)*ld + n
 doubles, workspace bd_workspace_size bytes).  Any out-of-bounds read or
@@ -16,18 +17,27 @@ ROOT = os.path.dirname(HERE)
 CLANG = "/opt/rocm/llvm/bin/clang++"
 
 
-@pytest.fixture(scope="module")
-def emu(tmp_path_factory):
+def _build(tmp_path_factory, name):
     if not os.path.exists(CLANG) and shutil.which("clang++") is None:
         pytest.skip("no clang++ for the host build")
     cxx = CLANG if os.path.exists(CLANG) else shutil.which("clang++")
-    exe = str(tmp_path_factory.mktemp("emu") / "chol_emu")
+    exe = str(tmp_path_factory.mktemp("emu") / name)
     cmd = [cxx, "-std=c++17", "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer",
            "-I", os.path.join(HERE, "cpu_emu"), "-I", os.path.join(ROOT, "include"),
-           "-x", "c++", os.path.join(HERE, "cpu_emu", "chol_emu.cpp"), "-o", exe]
+           "-x", "c++", os.path.join(HERE, "cpu_emu", name + ".cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     return exe
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    return _build(tmp_path_factory, "chol_emu")
+
+
+@pytest.fixture(scope="module")
+def cemu(tmp_path_factory):
+    return _build(tmp_path_factory, "constrain_emu")
 
 
 CASES = [(n, ld_pad) for n in (1, 6, 127, 128, 129, 256, 257, 383, 640, 1101, 3003) for ld_pad in (0, 3)]
@@ -42,3 +52,14 @@ def test_cholesky_accesses_in_bounds(emu, n, ld_pad, prec):
                                capture_output=True, text=True, timeout=300)
             assert r.returncode == 0, (n, ld_pad, prec, sp, la, r.stderr[-3000:])
             assert "status 0" in r.stdout and " 0 schedule errors" in r.stdout
+
+
+# (beads, Newton iteration cap, skip the matrix-free product threads): the
+# largest chain the solve supports runs with the O(N^2) product skipped.
+@pytest.mark.parametrize("N,maxit,skip", [(2, 1, 0), (3, 2, 0), (37, 2, 0), (300, 1, 0),
+                                          (1025, 1, 1), (4097, 2, 1)])
+def test_constrain_accesses_in_bounds(cemu, N, maxit, skip):
+    r = subprocess.run([cemu, str(N), str(maxit), str(skip)], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, (N, maxit, skip, r.stderr[-3000:])
+    assert "status 0" in r.stdout
