@@ -26,7 +26,7 @@ struct bd_handle_s {
   int prof_on;
   int pairs_hint;      // D products the last tension solve needed
   hipStream_t aux;     // lookahead stream of the Cholesky (default priority)
-  hipEvent_t ev[3];    // fork / panel-ready / rest-done events
+  hipEvent_t ev[4];    // fork / panel-ready / rest-done / next-columns-done events
   int step_panels;     // Cholesky panels applied per pass over the trailing matrix
 };
 
@@ -122,7 +122,7 @@ extern "C" {
 // Releases whatever a (possibly partially built) handle holds.
 static void release(bd_handle_s* h) {
   if (h->aux) (void)hipStreamSynchronize(h->aux);
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 4; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   if (h->aux) (void)hipStreamDestroy(h->aux);
   if (h->st) (void)hipFree(h->st);
@@ -151,7 +151,7 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   h->prof_on = 0;
   h->pairs_hint = 0;
   h->aux = nullptr;
-  h->ev[0] = h->ev[1] = h->ev[2] = nullptr;
+  h->ev[0] = h->ev[1] = h->ev[2] = h->ev[3] = nullptr;
   // BDRPY_STEP_PANELS=1 applies one panel per trailing pass (for
   // comparisons); by default two panels share each pass over the matrix.
   const char* sp = getenv("BDRPY_STEP_PANELS");
@@ -166,7 +166,7 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   const char* la = getenv("BDRPY_LOOKAHEAD");
   const bool lookahead = !(la && la[0] == '0');
   bool ok = !lookahead || hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess;
-  for (int i = 0; i < 3 && ok && lookahead; ++i)
+  for (int i = 0; i < 4 && ok && lookahead; ++i)
     ok = hipEventCreateWithFlags(&h->ev[i], hipEventDisableTiming) == hipSuccess;
   memset(h->host, 0, sizeof(DevState));
   if (ok) ok = hipMemcpy(h->st, h->host, sizeof(DevState), hipMemcpyHostToDevice) == hipSuccess;

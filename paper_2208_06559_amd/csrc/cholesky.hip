@@ -635,7 +635,7 @@ hipError_t factor_step(const CholCtx& c, hipStream_t s, int64_t k0, int64_t* wid
 // columns), the auxiliary stream updates those tile columns first, then
 // factors the next step's panels.  Events order the two streams; with
 // aux == nullptr everything runs on `s` in order.
-hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[3], int64_t n, double* A,
+hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int64_t n, double* A,
                            int64_t ld, bd_precision_t prec, void* ws, DevState* st,
                            int step_panels) {
   CholCtx c;
@@ -661,7 +661,7 @@ hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[3], int
     }
     return hipGetLastError();
   }
-  hipEvent_t ev_fork = ev[0], ev_panel = ev[1], ev_rest = ev[2];
+  hipEvent_t ev_fork = ev[0], ev_panel = ev[1], ev_rest = ev[2], ev_next = ev[3];
   if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
   if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
   if ((e = factor_step(c, aux, 0, &w)) != hipSuccess) return e;
@@ -673,9 +673,13 @@ hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[3], int
     // aux: the next step's tile columns must have every earlier update
     if (k > 0 && (e = hipStreamWaitEvent(aux, ev_rest, 0)) != hipSuccess) return e;
     if ((e = trailing(c, aux, k, r0, (int)w, kTilesNext, nnext)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev_next, aux)) != hipSuccess) return e;
     int64_t wn = 0;
     if ((e = factor_step(c, aux, r0, &wn)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
+    // main: the bulk update starts once the next columns are done, so that
+    // they (on the critical path) do not share the GPU with it
+    if ((e = hipStreamWaitEvent(s, ev_next, 0)) != hipSuccess) return e;
     if ((e = trailing(c, s, k, r0, (int)w, kTilesRest, nnext)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev_rest, s)) != hipSuccess) return e;
     k = r0;

@@ -100,7 +100,7 @@ int main(int argc, char** argv) {
   void* ws = malloc(wsb);
   memset(ws, 0, wsb);
   bd::DevState* st = (bd::DevState*)calloc(1, sizeof(bd::DevState));
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   const hipError_t e = bd::launch_cholesky(nullptr, use_aux ? (hipStream_t)0x1 : nullptr, ev, n, A,
                                            ld, (bd_precision_t)prec, ws, st, sp);
   if (prec == 0)
