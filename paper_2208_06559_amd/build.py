@@ -19,6 +19,15 @@ CFLAGS = [
 ]
 
 
+# Per-source flags.  cholesky.hip: matrix-core instructions keep their
+# accumulators in ordinary vector registers (the diagonal-block kernel works
+# on the same tiles with vector instructions between its matrix-core phases;
+# accumulator registers would cost a copy each way per phase).
+SOURCE_FLAGS = {
+    "cholesky.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
+
 def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
@@ -30,7 +39,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
     def compile_one(src_obj):
         src, obj = src_obj
-        cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+        cmd = [HIPCC, *CFLAGS, *SOURCE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

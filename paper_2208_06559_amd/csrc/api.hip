@@ -28,6 +28,7 @@ struct bd_handle_s {
   hipStream_t aux;     // lookahead stream of the Cholesky (default priority)
   hipEvent_t ev[4];    // fork / panel-ready / rest-done / next-columns-done events
   int step_panels;     // Cholesky panels applied per pass over the trailing matrix
+  bool tile_potrf;     // Cholesky diagonal blocks on matrix cores
 };
 
 namespace {
@@ -156,6 +157,10 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   // comparisons); by default two panels share each pass over the matrix.
   const char* sp = getenv("BDRPY_STEP_PANELS");
   h->step_panels = (sp && sp[0] == '1') ? 1 : 2;
+  // BDRPY_POTRF=reg factors the diagonal blocks with the register-tiled
+  // kernel (for comparisons); by default they run on matrix cores.
+  const char* pt = getenv("BDRPY_POTRF");
+  h->tile_potrf = !(pt && pt[0] == 'r');
   if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
       hipHostMalloc(&h->host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
     release(h);
@@ -235,7 +240,7 @@ bd_status_t bd_cholesky(bd_handle_t h, int64_t n, double* d_A, int64_t ld, bd_pr
   if (ws_bytes < bd::cholesky_workspace_bytes(n, prec)) return BD_ERR_PARAM;
   if (reset(h) != hipSuccess) return BD_ERR_HIP;
   return hip_status(bd::launch_cholesky(h->stream, h->aux, h->ev, n, d_A, ld, prec, d_ws, h->st,
-                                              h->step_panels));
+                                              h->step_panels, h->tile_potrf));
 }
 
 bd_status_t bd_brownian(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_L,
@@ -283,7 +288,7 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
   if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
   if (he == hipSuccess)
     he = bd::launch_cholesky(s, h->aux, h->ev, n, D, ld, prec, base + L.chol, h->st,
-                              h->step_panels);
+                              h->step_panels, h->tile_potrf);
   if (he == hipSuccess)
     he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);

@@ -21,6 +21,8 @@
 // side" rows are fed as operand A and the "row side" rows as operand B, so
 // each result register of a wavefront covers 16 consecutive rows of 4
 // columns: 128-byte runs in column-major memory.
+#include <utility>
+
 #include "common.hpp"
 #include "profile.hpp"
 
@@ -161,6 +163,36 @@ __device__ __forceinline__ void factor_quad(double (&a)[TT][TT], double* __restr
   }
 }
 
+// Wave p (of four) inverts diagonal 32 x 32 block p of L11 (column-major in
+// Ld, 1/L(j,j) in rdg) column by column: lane c solves L_pp y = e_c by
+// forward substitution (y[i] = 0 for i < c falls out of the recursion); the
+// upper lanes repeat the work and do not store.  Writes Winv_p (32 x 32,
+// column-major) to W + p * SBB.
+__device__ __forceinline__ void invert_diag_blocks(const double* __restrict__ Ld,
+                                                   const double* __restrict__ rdg,
+                                                   double* __restrict__ W, int tid) {
+  const int p = tid >> 6, c = tid & 31;
+  const double* L = Ld + p * SBB;
+  const double* rd = rdg + SB * p;
+  double y[SB];
+#pragma unroll
+  for (int i = 0; i < SB; ++i) {
+    double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+    for (int q = 0; q + 1 < i; q += 2) {
+      s0 = fma(-L[q * SB + i], y[q], s0);
+      s1 = fma(-L[(q + 1) * SB + i], y[q + 1], s1);
+    }
+    if (i & 1) s0 = fma(-L[(i - 1) * SB + i], y[i - 1], s0);
+    y[i] = (s0 + s1) * rd[i];
+  }
+  if ((tid & 63) < SB) {
+    double* Wc = W + p * SBB + c * SB;  // column c of Winv_p (column-major)
+#pragma unroll
+    for (int i = 0; i < SB; ++i) Wc[i] = y[i];
+  }
+}
+
 // Rank-4 update by the published columns j0 .. j0 + 3 (j0 = 16 JB + 4 q) of
 // the tile columns IB0 <= ib < IB1.  Only tiles ib >= JB, ia >= ib can hold
 // live elements: for ia < ib every row is above every column, for ia > ib
@@ -269,31 +301,279 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
       if ((i >> 5) == (c >> 5)) Ld[i >> 5][(c & 31) * SB + (i & 31)] = (i >= c) ? a[ia][ib] : 0.0;
     }
   __syncthreads();
-  // Wave p inverts diagonal block p column by column: lane c solves
-  // L_pp y = e_c by forward substitution (y[i] = 0 for i < c falls out of
-  // the recursion); the upper lanes repeat the work and do not store.
-  {
-    const int p = tid >> 6, c = tid & 31;
-    const double* L = Ld[p];
-    const double* rd = rdg + SB * p;
-    double y[SB];
+  invert_diag_blocks(&Ld[0][0], rdg, W, tid);
+}
+
+// ------------------------------------------------------------------------
+// 1b. The same diagonal block on matrix cores.  The block is held as 16 x 16
+//     tiles in the FP64 MFMA result layout (lane lr + 16 lk, register r
+//     holds tile element (lk + 4r, lr)); wave w owns tile columns w and
+//     w + 4, and each diagonal tile is kept whole and symmetric.  The owner
+//     of tile column J factors its 16 columns alone, without exchanges
+//     through LDS: column j's pivot is a lane read, its entries reach the
+//     lanes of their row by DPP (row_newbcast), and the multiplier of lane
+//     lr is the symmetric entry (j, 16 J + lr) of the diagonal tile, spread
+//     over the four lane groups by two lane swaps.  The columns stay
+//     unscaled (each rank-1 update carries 1 / A(j,j)) and are scaled once
+//     when the column block is published; the next pivot's reciprocal
+//     square root is taken while the current column updates the tiles
+//     below the diagonal.  Every wave then applies the published block to
+//     its tiles as a rank-16 update (four v_mfma_f64_16x16x4 per tile), the
+//     next column block's owner first.  One barrier per 16 columns.
+// ------------------------------------------------------------------------
+constexpr int kLpStride = 17;  // padded LDS row of a published column block
+
+// Lane (lane & 15) + 16 C's value to every lane of its 16-lane row.
+template <int C>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + C, 0xF, 0xF, true);
+}
+
+// Lane (lane & 15) + 16 S's value to the lanes (lane & 15) + 16 g, g < 4.
+template <int S>
+__device__ __forceinline__ uint32_t group_bcast_u32(uint32_t v) {
+  const uint32_t h = __builtin_amdgcn_permlane32_swap(v, v, false, false)[S >> 1];
+  return __builtin_amdgcn_permlane16_swap(h, h, false, false)[S & 1];
+}
+template <int S>
+__device__ __forceinline__ double group_bcast(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = group_bcast_u32<S>((uint32_t)u), hi = group_bcast_u32<S>((uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Pivot of column j = 16 J + C from the diagonal tile T0: records the
+// first non-positive pivot in `bad`, keeps 1 / L(j,j) in the lane of
+// column j (myrs) and returns this lane's rank-1 coefficient
+// -A(16 J + lr, j) / A(j,j) for the columns past j (0 elsewhere).
+template <int J, int C>
+__device__ __forceinline__ double tile_pivot(const d4& T0, double& myrs, int& bad, int lr) {
+  const double d = readlane_f64(T0[C / 4], C + 16 * (C % 4));  // A(j, j)
+  const double m = group_bcast<C % 4>(T0[C / 4]);              // A(j, 16 J + lr)
+  bad = (bad < 0 && !(d > 0.0)) ? 16 * J + C : bad;
+  const double rs = rsqrt_refined(d);  // NaN for a non-positive pivot
+  myrs = (lr == C) ? rs : myrs;
+  return (lr > C) ? -(rs * m) * rs : 0.0;
+}
+
+// Rank-1 update of tiles [TB, TE) by unscaled column C: element (row, lr)
+// gains beta(lr) A(row, j).  Lanes with beta = 0 keep their values exactly.
+// Column 0 of a block broadcasts with a DPP move and a separate FMA, so that
+// the compiler orders these first reads of the matrix-core results; later
+// columns use one v_fmac_f64 with the DPP broadcast on its first operand.
+// Two wait states must separate a VALU write of a register from a DPP
+// instruction reading it, which the compiler does not check inside inline
+// assembly: a column's writes of an element and the next column's read of
+// it are kept at least two instructions apart by the next pivot (tile 0) or
+// the next column's tile-0 update (other tiles), scheduling barriers
+// between columns stop the compiler from moving them closer, and the first
+// instruction of each column waits for its coefficient.
+template <int C>
+__device__ __forceinline__ void fmac_row_bcast(double& x, double beta, bool wait) {
+  if (wait)  // beta may have been written by the instruction before (folded when unrolled)
+    asm("s_nop 1\n\tv_fmac_f64_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+        : "+v"(x)
+        : "v"(beta), "i"(C));
+  else
+    asm("v_fmac_f64_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+        : "+v"(x)
+        : "v"(beta), "i"(C));
+}
+
+template <int C, int TB, int TE, int NT>
+__device__ __forceinline__ void tile_rank1(d4 (&T)[NT], double beta) {
 #pragma unroll
-    for (int i = 0; i < SB; ++i) {
-      double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0;
+  for (int t = TB; t < TE; ++t) {
+    if constexpr (C == 0) {
+      double v[4];  // all broadcasts first: no temporary is rewritten right after its use
 #pragma unroll
-      for (int q = 0; q + 1 < i; q += 2) {
-        s0 = fma(-L[q * SB + i], y[q], s0);
-        s1 = fma(-L[(q + 1) * SB + i], y[q + 1], s1);
+      for (int r = 0; r < 4; ++r) v[r] = row_bcast<C>(T[t][r]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) T[t][r] = fma(beta, v[r], T[t][r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double x = T[t][r];
+        fmac_row_bcast<C>(x, beta, t == 0 && r == 0);
+        T[t][r] = x;
       }
-      if (i & 1) s0 = fma(-L[(i - 1) * SB + i], y[i - 1], s0);
-      y[i] = (s0 + s1) * rd[i];
-    }
-    if ((tid & 63) < SB) {
-      double* Wc = W + p * SBB + c * SB;  // column c of Winv_p (column-major)
-#pragma unroll
-      for (int i = 0; i < SB; ++i) Wc[i] = y[i];
     }
   }
+}
+
+template <int J, int C, int NT>
+__device__ __forceinline__ void tile_col(d4 (&T)[NT], double& beta, double& myrs, int& bad,
+                                         int lr) {
+  if constexpr (C < 15) {  // column 15 has no columns past it in the block
+    tile_rank1<C, 0, 1>(T, beta);
+    const double next = tile_pivot<J, C + 1>(T[0], myrs, bad, lr);
+    tile_rank1<C, 1, 8 - J>(T, beta);
+    beta = next;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int J, int NT, int... C>
+__device__ __forceinline__ void tile_cols(d4 (&T)[NT], double& beta, double& myrs, int& bad,
+                                          int lr, std::integer_sequence<int, C...>) {
+  (tile_col<J, C>(T, beta, myrs, bad, lr), ...);
+}
+
+// Owner of tile column J: factor it, scale it, publish its rows below tile
+// J to lp and its 1 / L(j,j) to rdg.
+template <int J, int NT>
+__device__ __forceinline__ void tile_factor_publish(d4 (&T)[NT], double* __restrict__ lp,
+                                                    double* __restrict__ rdg, int& bad, int lr,
+                                                    int lk) {
+  double myrs = 1.0;
+  double beta = tile_pivot<J, 0>(T[0], myrs, bad, lr);
+  tile_cols<J>(T, beta, myrs, bad, lr, std::make_integer_sequence<int, 16>{});
+#pragma unroll
+  for (int t = 0; t < 8 - J; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[t][r] *= myrs;
+  if (lk == 0) rdg[16 * J + lr] = myrs;
+#pragma unroll
+  for (int t = 1; t < 8 - J; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lp[(16 * (J + t) + lk + 4 * r) * kLpStride + lr] = T[t][r];
+}
+
+// Rank-16 update of this wave's tiles (K + t, K), t < 8 - K, of tile column
+// K by the published column block in lp.
+template <int K, int NT>
+__device__ __forceinline__ void tile_apply(d4 (&T)[NT], const double* __restrict__ lp, int lr,
+                                           int lk) {
+  double b[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) b[s] = lp[(16 * K + lr) * kLpStride + 4 * s + lk];
+#pragma unroll
+  for (int t = 0; t < 8 - K; ++t) {
+    double a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[s] = -lp[(16 * (K + t) + lr) * kLpStride + 4 * s + lk];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) T[t] = mfma(a[s], b[s], T[t]);
+  }
+}
+
+// Wave W, not the owner of column block J + 1: its tile columns past J.
+template <int J, int W>
+__device__ __forceinline__ void tile_apply_rest(d4 (&T0)[8], d4 (&T1)[4], const double* lp,
+                                                int lr, int lk) {
+  if constexpr (W > J) tile_apply<W>(T0, lp, lr, lk);
+  if constexpr (W + 4 > J) tile_apply<W + 4>(T1, lp, lr, lk);
+}
+
+// After column block J is published in lp_cur: the owner of block J + 1
+// updates that tile column first, factors and publishes it into lp_next,
+// then updates its other column; every other wave updates its columns
+// past J.  Ends with the barrier that publishes block J + 1.  Scheduling
+// barriers keep the phases apart, so that no operand of a later phase is
+// held in registers through the factorisation.
+template <int J>
+__device__ __forceinline__ void tile_step(d4 (&T0)[8], d4 (&T1)[4], const double* lp_cur,
+                                          double* lp_next, double* rdg, int& bad, int w, int lr,
+                                          int lk) {
+  constexpr int Jn = J + 1;
+  if constexpr (Jn < 8) {
+    if (w == Jn % 4) {
+      if constexpr (Jn < 4) {
+        tile_apply<Jn>(T0, lp_cur, lr, lk);
+        __builtin_amdgcn_sched_barrier(0);
+        tile_factor_publish<Jn>(T0, lp_next, rdg, bad, lr, lk);
+        __builtin_amdgcn_sched_barrier(0);
+        tile_apply<Jn + 4>(T1, lp_cur, lr, lk);
+      } else {
+        tile_apply<Jn>(T1, lp_cur, lr, lk);
+        __builtin_amdgcn_sched_barrier(0);
+        tile_factor_publish<Jn>(T1, lp_next, rdg, bad, lr, lk);
+      }
+    } else {
+      switch (w) {
+        case 0: tile_apply_rest<J, 0>(T0, T1, lp_cur, lr, lk); break;
+        case 1: tile_apply_rest<J, 1>(T0, T1, lp_cur, lr, lk); break;
+        case 2: tile_apply_rest<J, 2>(T0, T1, lp_cur, lr, lk); break;
+        default: tile_apply_rest<J, 3>(T0, T1, lp_cur, lr, lk); break;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int... J>
+__device__ __forceinline__ void tile_steps(d4 (&T0)[8], d4 (&T1)[4], double* lp, double* rdg,
+                                           int& bad, int w, int lr, int lk,
+                                           std::integer_sequence<int, J...>) {
+  (tile_step<J>(T0, T1, lp + (J & 1) * NB * kLpStride, lp + ((J + 1) & 1) * NB * kLpStride, rdg,
+                bad, w, lr, lk),
+   ...);
+}
+
+// Tiles (K + t, K), t < NT, of tile column K between global memory and T
+// (rows and columns past nb padded with the identity on load; the diagonal
+// tile whole, its upper part mirrored from the lower one).
+template <int NT>
+__device__ __forceinline__ void tile_load(d4 (&T)[NT], int K, const double* __restrict__ Akk,
+                                          int64_t ld, int nb, int lr, int lk) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * (K + t) + lk + 4 * r, col = 16 * K + lr;
+      // the diagonal tile's upper part mirrors the lower one
+      const bool live = (t < 8 - K) && row < nb && col < nb;
+      const int64_t off = (row >= col) ? (int64_t)col * ld + row : (int64_t)row * ld + col;
+      double v = (row == col) ? 1.0 : 0.0;
+      if (live) v = Akk[off];
+      T[t][r] = v;
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void tile_store(const d4 (&T)[NT], int K, double* __restrict__ Akk,
+                                           int64_t ld, int nb, double* __restrict__ Ld, int lr,
+                                           int lk) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int I = K + t, row = 16 * I + lk + 4 * r, col = 16 * K + lr;
+      if (t < 8 - K && row >= col) {
+        if (row < nb && col < nb) Akk[(int64_t)col * ld + row] = T[t][r];
+        if ((I >> 1) == (K >> 1)) Ld[(row >> 5) * SBB + (col & 31) * SB + (row & 31)] = T[t][r];
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A, int64_t ld,
+                                                          int64_t k, int nb,
+                                                          double* __restrict__ W,
+                                                          DevState* __restrict__ st) {
+  __shared__ double lp[2 * NB * kLpStride];  // published column blocks (double buffer)
+  __shared__ double Ld[NSB * SBB];           // diagonal 32 x 32 blocks of L, column-major
+  __shared__ double rdg[NB];                 // 1 / L(j,j)
+  __shared__ int first_bad;                  // first non-positive pivot (NB: none)
+  const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  double* Akk = A + k * ld + k;
+  d4 T0[8], T1[4];  // tile columns w and w + 4
+  int bad = -1;     // first non-positive pivot among this wave's columns
+  if (tid == 0) first_bad = NB;
+  tile_load(T0, w, Akk, ld, nb, lr, lk);
+  tile_load(T1, w + 4, Akk, ld, nb, lr, lk);
+  if (w == 0) tile_factor_publish<0>(T0, lp, rdg, bad, lr, lk);
+  __syncthreads();
+  tile_steps(T0, T1, lp, rdg, bad, w, lr, lk, std::make_integer_sequence<int, 7>{});
+  tile_store(T0, w, Akk, ld, nb, Ld, lr, lk);
+  tile_store(T1, w + 4, Akk, ld, nb, Ld, lr, lk);
+  if (lane == 0 && bad >= 0) atomicMin(&first_bad, bad);
+  __syncthreads();
+  if (tid == 0 && first_bad < NB && st->potrf_info == 0) {
+    st->potrf_info = k + first_bad + 1;
+    st->status = BD_ERR_NOT_SPD;
+  }
+  invert_diag_blocks(Ld, rdg, W, tid);
 }
 
 // ------------------------------------------------------------------------
@@ -551,6 +831,7 @@ struct CholCtx {
   // indexed by global row (P[c * n + row]); null in FP64
   float* P32[2];
   int step;  // columns per step: 1 or 2 panels
+  bool tile_potrf;  // diagonal blocks on matrix cores (else register tiles)
   DevState* st;
 };
 
@@ -562,8 +843,12 @@ float* step_copy(const CholCtx& c, int64_t k0) {
 // number (kp - k0) / NB of the step starting at k0.
 hipError_t factor_panel(const CholCtx& c, hipStream_t s, int64_t k0, int64_t kp) {
   const int nb = (int)((c.n - kp < NB) ? (c.n - kp) : NB);
-  BD_LAUNCH("potrf_diag", potrf_diag_kernel, dim3(1), dim3(256), 0, s, c.A, c.ld, kp, nb, c.W,
-            c.st);
+  if (c.tile_potrf)
+    BD_LAUNCH("potrf_tile", potrf_tile_kernel, dim3(1), dim3(256), 0, s, c.A, c.ld, kp, nb, c.W,
+              c.st);
+  else
+    BD_LAUNCH("potrf_diag", potrf_diag_kernel, dim3(1), dim3(256), 0, s, c.A, c.ld, kp, nb, c.W,
+              c.st);
   const int64_t m = c.n - kp - nb;
   if (m > 0) {  // then nb == NB: only the last panel can be narrower
     float* P = step_copy(c, k0);
@@ -637,7 +922,7 @@ hipError_t factor_step(const CholCtx& c, hipStream_t s, int64_t k0, int64_t* wid
 // aux == nullptr everything runs on `s` in order.
 hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int64_t n, double* A,
                            int64_t ld, bd_precision_t prec, void* ws, DevState* st,
-                           int step_panels) {
+                           int step_panels, bool tile_potrf) {
   CholCtx c;
   c.n = n;
   c.ld = ld;
@@ -645,6 +930,7 @@ hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int
   c.st = st;
   c.W = static_cast<double*>(ws);
   c.step = (step_panels == 2 ? 2 : 1) * NB;
+  c.tile_potrf = tile_potrf;
   c.P32[0] = c.P32[1] = nullptr;
   if (prec == BD_PREC_MIXED) {
     char* p = static_cast<char*>(ws) + align_up(sizeof(double) * NB * NB, 256);

@@ -41,7 +41,7 @@ hipError_t launch_rpy_assemble(hipStream_t s, const bd_params_t& p, const double
 size_t cholesky_workspace_bytes(int64_t n, bd_precision_t prec);
 hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int64_t n, double* A,
                            int64_t ld, bd_precision_t prec, void* ws, DevState* st,
-                           int step_panels);
+                           int step_panels, bool tile_potrf);
 
 // brownian.hip
 size_t brownian_workspace_bytes(int64_t n);

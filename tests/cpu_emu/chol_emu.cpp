@@ -7,6 +7,7 @@
 // on 64 x 64 sub-tiles, the finest tile a launch uses), and
 // every diagonal block is factored exactly once.
 // Usage: chol_emu n ld prec(0 fp64, 1 mixed) step_panels(1|2) lookahead(0|1)
+//        [tile_potrf(0|1), default 1]
 #include <map>
 #include <utility>
 
@@ -74,7 +75,8 @@ void observe(const void* kernel, dim3 grid, const int64_t* a, int nargs) {
           g_applied[key] = k0 + kdim;
         }
     }
-  } else if (kernel == (const void*)&potrf_diag_kernel) {
+  } else if (kernel == (const void*)&potrf_diag_kernel ||
+             kernel == (const void*)&potrf_tile_kernel) {
     // (A, ld, k, nb, W, st)
     const int64_t kp = a[2], J = kp / NB;
     for (int64_t I = kp / 64; I * 64 < g_n; ++I)
@@ -86,9 +88,10 @@ void observe(const void* kernel, dim3 grid, const int64_t* a, int nargs) {
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc != 6) return 2;
+  if (argc != 6 && argc != 7) return 2;
   const int64_t n = atoll(argv[1]), ld = atoll(argv[2]);
   const int prec = atoi(argv[3]), sp = atoi(argv[4]), use_aux = atoi(argv[5]);
+  const bool tile = argc == 7 ? atoi(argv[6]) != 0 : true;
   double* A = (double*)malloc(sizeof(double) * ((n - 1) * ld + n));
   for (int64_t c = 0; c < n; ++c)
     for (int64_t i = 0; i < n; ++i) A[c * ld + i] = (i == c) ? 1.0 + n : 0.1;
@@ -102,12 +105,12 @@ int main(int argc, char** argv) {
   bd::DevState* st = (bd::DevState*)calloc(1, sizeof(bd::DevState));
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   const hipError_t e = bd::launch_cholesky(nullptr, use_aux ? (hipStream_t)0x1 : nullptr, ev, n, A,
-                                           ld, (bd_precision_t)prec, ws, st, sp);
+                                           ld, (bd_precision_t)prec, ws, st, sp, tile);
   if (prec == 0)
     for (int64_t J = 0; J * bd::NB < n; ++J)
       if (g_factored[J] != 1) fail("diagonal block not factored once", J, g_factored[J], 0);
-  printf("n=%lld ld=%lld prec=%d step_panels=%d lookahead=%d: status %d, %ld launches, %d schedule errors\n",
-         (long long)n, (long long)ld, prec, sp, use_aux, e, g_emu_launches, g_errors);
+  printf("n=%lld ld=%lld prec=%d step_panels=%d lookahead=%d tile_potrf=%d: status %d, %ld launches, %d schedule errors\n",
+         (long long)n, (long long)ld, prec, sp, use_aux, (int)tile, e, g_emu_launches, g_errors);
   free(A);
   free(ws);
   free(st);

@@ -44,6 +44,15 @@ inline void __threadfence() {}
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) ((c) + (a) * (b))
 #define __builtin_amdgcn_readlane(v, l) (v)
 #define __builtin_amdgcn_ds_bpermute(addr, v) (v)
+#define __builtin_amdgcn_update_dpp(old, v, ctrl, rm, bm, bc) (v)
+#define __builtin_amdgcn_mov_dpp(v, ctrl, rm, bm, bc) (v)
+#define __builtin_amdgcn_readfirstlane(v) (v)
+typedef unsigned emu_u32x2 __attribute__((ext_vector_type(2)));
+inline emu_u32x2 __builtin_amdgcn_permlane16_swap(unsigned a, unsigned b, bool, bool) { return emu_u32x2{a, b}; }
+inline emu_u32x2 __builtin_amdgcn_permlane32_swap(unsigned a, unsigned b, bool, bool) { return emu_u32x2{a, b}; }
+inline int atomicMin(int* p, int v) { const int o = *p; if (v < o) *p = v; return o; }
+// GPU inline assembly has no host meaning: it leaves its operands as they are.
+#define asm(...) ((void)0)
 #define __builtin_amdgcn_rsq(d) (1.0 / std::sqrt(d))
 #define __builtin_amdgcn_rcp(d) (1.0 / (d))
 #define __builtin_amdgcn_fence(...) ((void)0)

@@ -108,13 +108,16 @@ def test_cholesky_mixed_residual(h, N, seed):
 @pytest.mark.parametrize("step_panels", ["1", "2"])
 @pytest.mark.parametrize("lookahead", ["0", "1"])
 @pytest.mark.parametrize("prec", [B.PREC_FP64, B.PREC_MIXED])
-def test_cholesky_schedules(monkeypatch, step_panels, lookahead, prec):
+@pytest.mark.parametrize("potrf", ["tile", "reg"])
+def test_cholesky_schedules(monkeypatch, step_panels, lookahead, prec, potrf):
     """Every factorisation schedule (one or two panels per trailing pass,
-    with or without the lookahead stream) on a ragged n spanning several
-    steps: FP64 to the rounding level of the oracle's factor, MIXED through
-    its residual bound."""
+    with or without the lookahead stream, diagonal blocks on matrix cores or
+    in register tiles) on a ragged n spanning several steps: FP64 to the
+    rounding level of the oracle's factor, MIXED through its residual
+    bound."""
     monkeypatch.setenv("BDRPY_STEP_PANELS", step_panels)
     monkeypatch.setenv("BDRPY_LOOKAHEAD", lookahead)
+    monkeypatch.setenv("BDRPY_POTRF", potrf)
     hh = B.Handle(0)
     try:
         N = 367  # n = 1101: eight full panels and a 77-column tail
