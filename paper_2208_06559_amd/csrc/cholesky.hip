@@ -306,22 +306,40 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
 
 // ------------------------------------------------------------------------
 // 1b. The same diagonal block on matrix cores.  The block is held as 16 x 16
-//     tiles in the FP64 MFMA result layout (lane lr + 16 lk, register r
-//     holds tile element (lk + 4r, lr)); wave w owns tile columns w and
-//     w + 4, and each diagonal tile is kept whole and symmetric.  The owner
-//     of tile column J factors its 16 columns alone, without exchanges
-//     through LDS: column j's pivot is a lane read, its entries reach the
-//     lanes of their row by DPP (row_newbcast), and the multiplier of lane
-//     lr is the symmetric entry (j, 16 J + lr) of the diagonal tile, spread
-//     over the four lane groups by two lane swaps.  The columns stay
-//     unscaled (each rank-1 update carries 1 / A(j,j)) and are scaled once
-//     when the column block is published; the next pivot's reciprocal
-//     square root is taken while the current column updates the tiles
-//     below the diagonal.  Every wave then applies the published block to
-//     its tiles as a rank-16 update (four v_mfma_f64_16x16x4 per tile), the
-//     next column block's owner first.  One barrier per 16 columns.
+//     tiles in the FP64 MFMA result layout: lane lr + 16 lk, register r
+//     holds tile column lr and MFMA row lk + 4r, which stands for tile row
+//     tile_row(lk, r) = 2 lk + (r & 1) + 8 (r >> 1) (any fixed row order
+//     serves; this one gives each lane row pairs, for 16-byte loads and
+//     stores).  Wave w owns tile columns w and w + 4; each diagonal tile is
+//     kept whole and symmetric.  The owner of tile column J factors its 16
+//     columns alone, without exchanges through LDS: column j's pivot is a
+//     lane read, its entries reach the lanes of their row by DPP
+//     (row_newbcast), and the multiplier of lane lr is the symmetric entry
+//     (j, 16 J + lr) of the diagonal tile, spread over the four lane groups
+//     by two lane swaps.  The columns stay unscaled: each rank-1 update
+//     carries 1 / A(j,j), whose Newton steps are interleaved with the
+//     previous column's update of the tiles below the diagonal, and each
+//     column is scaled by 1 / sqrt(A(j,j)) once, when the block is
+//     published.  Every wave then applies the published block to its tiles
+//     as a rank-16 update (four v_mfma_f64_16x16x4 per tile), the next
+//     block's owner first.  One barrier per 16 columns.
 // ------------------------------------------------------------------------
 constexpr int kLpStride = 17;  // padded LDS row of a published column block
+
+__host__ __device__ constexpr int tile_row(int lk, int r) { return 2 * lk + (r & 1) + 8 * (r >> 1); }
+// MFMA row i = lk + 4r of a result tile as a tile row
+__host__ __device__ constexpr int mfma_row(int i) { return tile_row(i & 3, i >> 2); }
+// lane group and register holding tile row p
+__host__ __device__ constexpr int row_group(int p) { return (p & 7) >> 1; }
+__host__ __device__ constexpr int row_reg(int p) { return (p & 1) + 2 * (p >> 3); }
+
+// 1/x to full FP64 accuracy: hardware estimate plus two Newton steps.
+__device__ __forceinline__ double rcp_refined(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
 
 // Lane (lane & 15) + 16 C's value to every lane of its 16-lane row.
 template <int C>
@@ -342,20 +360,6 @@ __device__ __forceinline__ double group_bcast(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Pivot of column j = 16 J + C from the diagonal tile T0: records the
-// first non-positive pivot in `bad`, keeps 1 / L(j,j) in the lane of
-// column j (myrs) and returns this lane's rank-1 coefficient
-// -A(16 J + lr, j) / A(j,j) for the columns past j (0 elsewhere).
-template <int J, int C>
-__device__ __forceinline__ double tile_pivot(const d4& T0, double& myrs, int& bad, int lr) {
-  const double d = readlane_f64(T0[C / 4], C + 16 * (C % 4));  // A(j, j)
-  const double m = group_bcast<C % 4>(T0[C / 4]);              // A(j, 16 J + lr)
-  bad = (bad < 0 && !(d > 0.0)) ? 16 * J + C : bad;
-  const double rs = rsqrt_refined(d);  // NaN for a non-positive pivot
-  myrs = (lr == C) ? rs : myrs;
-  return (lr > C) ? -(rs * m) * rs : 0.0;
-}
-
 // Rank-1 update of tiles [TB, TE) by unscaled column C: element (row, lr)
 // gains beta(lr) A(row, j).  Lanes with beta = 0 keep their values exactly.
 // Column 0 of a block broadcasts with a DPP move and a separate FMA, so that
@@ -364,9 +368,9 @@ __device__ __forceinline__ double tile_pivot(const d4& T0, double& myrs, int& ba
 // Two wait states must separate a VALU write of a register from a DPP
 // instruction reading it, which the compiler does not check inside inline
 // assembly: a column's writes of an element and the next column's read of
-// it are kept at least two instructions apart by the next pivot (tile 0) or
-// the next column's tile-0 update (other tiles), scheduling barriers
-// between columns stop the compiler from moving them closer, and the first
+// it are kept apart by the next pivot's steps (tile 0) or by the next
+// column's tile-0 update and first pivot step (other tiles), scheduling
+// barriers stop the compiler from moving them closer, and the first
 // instruction of each column waits for its coefficient.
 template <int C>
 __device__ __forceinline__ void fmac_row_bcast(double& x, double beta, bool wait) {
@@ -401,22 +405,88 @@ __device__ __forceinline__ void tile_rank1(d4 (&T)[NT], double beta) {
   }
 }
 
+// Pivot of column j = 16 J + C, in seven dependent parts S = 0 .. 6 that
+// the caller interleaves with independent work.  Part 6 yields this lane's
+// rank-1 coefficient -A(j, 16 J + lr) / A(j,j) for the columns past j (0
+// elsewhere), keeps A(j,j) in the lane of column j (myd) and records the
+// first non-positive pivot in `bad`.  The multiplier A(j, 16 J + lr) comes
+// from the lane of the same column in the lane group holding tile row j,
+// through the LDS crossbar (bsrc: that lane's byte address per group).
+struct Pivot {
+  double d, m, y, e;
+};
+template <int J, int C, int S>
+__device__ __forceinline__ void pivot_part(const d4& T0, Pivot& p, double& beta, double& myd,
+                                           int& bad, int lr, const int (&bsrc)[4]) {
+  constexpr int g = row_group(C), q = row_reg(C);
+  if constexpr (S == 0) {
+    p.d = readlane_f64(T0[q], C + 16 * g);  // A(j, j)
+    // the element goes through a scalar first: clang bit-casts a vector
+    // element operand as the vector's leading bytes
+    const double v = T0[q];
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_ds_bpermute(bsrc[g], (int)(uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_ds_bpermute(bsrc[g], (int)(uint32_t)(u >> 32));
+    p.m = __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);  // A(j, 16 J + lr)
+  } else if constexpr (S == 1) {
+    p.y = __builtin_amdgcn_rcp(p.d);  // then two Newton steps
+  } else if constexpr (S == 2 || S == 4) {
+    p.e = fma(-p.d, p.y, 1.0);
+  } else if constexpr (S == 3 || S == 5) {
+    p.y = fma(p.y, p.e, p.y);
+  } else {
+    bad = (bad < 0 && !(p.d > 0.0)) ? 16 * J + C : bad;
+    myd = (lr == C) ? p.d : myd;
+    beta = (lr > C) ? -p.m * p.y : 0.0;
+  }
+}
+
+// Column C of block J: tile 0 first, then the next pivot's parts, each
+// followed by one tile below the diagonal.
+template <int J, int C, int S, int NT>
+__device__ __forceinline__ void tile_col_part(d4 (&T)[NT], Pivot& p, double beta, double& bnext,
+                                              double& myd, int& bad, int lr,
+                                              const int (&bsrc)[4]) {
+  pivot_part<J, C + 1, S>(T[0], p, bnext, myd, bad, lr, bsrc);
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (1 + S < 8 - J) tile_rank1<C, 1 + S, 2 + S>(T, beta);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int J, int C, int NT, int... S>
+__device__ __forceinline__ void tile_col_parts(d4 (&T)[NT], Pivot& p, double beta, double& bnext,
+                                               double& myd, int& bad, int lr,
+                                               const int (&bsrc)[4],
+                                               std::integer_sequence<int, S...>) {
+  (tile_col_part<J, C, S>(T, p, beta, bnext, myd, bad, lr, bsrc), ...);
+}
+
 template <int J, int C, int NT>
-__device__ __forceinline__ void tile_col(d4 (&T)[NT], double& beta, double& myrs, int& bad,
-                                         int lr) {
+__device__ __forceinline__ void tile_col(d4 (&T)[NT], double& beta, double& myd, int& bad,
+                                         int lr, const int (&bsrc)[4]) {
   if constexpr (C < 15) {  // column 15 has no columns past it in the block
     tile_rank1<C, 0, 1>(T, beta);
-    const double next = tile_pivot<J, C + 1>(T[0], myrs, bad, lr);
-    tile_rank1<C, 1, 8 - J>(T, beta);
-    beta = next;
     __builtin_amdgcn_sched_barrier(0);
+    Pivot p;
+    double bnext;
+    tile_col_parts<J, C>(T, p, beta, bnext, myd, bad, lr, bsrc,
+                         std::make_integer_sequence<int, 7>{});
+    beta = bnext;
   }
 }
 
 template <int J, int NT, int... C>
-__device__ __forceinline__ void tile_cols(d4 (&T)[NT], double& beta, double& myrs, int& bad,
-                                          int lr, std::integer_sequence<int, C...>) {
-  (tile_col<J, C>(T, beta, myrs, bad, lr), ...);
+__device__ __forceinline__ void tile_cols(d4 (&T)[NT], double& beta, double& myd, int& bad,
+                                          int lr, const int (&bsrc)[4],
+                                          std::integer_sequence<int, C...>) {
+  (tile_col<J, C>(T, beta, myd, bad, lr, bsrc), ...);
+}
+
+template <int J, int... S>
+__device__ __forceinline__ void first_pivot(const d4& T0, Pivot& p, double& beta, double& myd,
+                                            int& bad, int lr, const int (&bsrc)[4],
+                                            std::integer_sequence<int, S...>) {
+  (pivot_part<J, 0, S>(T0, p, beta, myd, bad, lr, bsrc), ...);
 }
 
 // Owner of tile column J: factor it, scale it, publish its rows below tile
@@ -425,9 +495,16 @@ template <int J, int NT>
 __device__ __forceinline__ void tile_factor_publish(d4 (&T)[NT], double* __restrict__ lp,
                                                     double* __restrict__ rdg, int& bad, int lr,
                                                     int lk) {
-  double myrs = 1.0;
-  double beta = tile_pivot<J, 0>(T[0], myrs, bad, lr);
-  tile_cols<J>(T, beta, myrs, bad, lr, std::make_integer_sequence<int, 16>{});
+  double myd = 1.0, beta = 0.0;
+  int bsrc[4];  // byte address of lane lr in each lane group, for the multipliers
+#pragma unroll
+  for (int g = 0; g < 4; ++g) bsrc[g] = 4 * (lr + 16 * g);
+  {
+    Pivot p;
+    first_pivot<J>(T[0], p, beta, myd, bad, lr, bsrc, std::make_integer_sequence<int, 7>{});
+  }
+  tile_cols<J>(T, beta, myd, bad, lr, bsrc, std::make_integer_sequence<int, 16>{});
+  const double myrs = rsqrt_refined(myd);  // 1 / L(16 J + lr, 16 J + lr); NaN if not positive
 #pragma unroll
   for (int t = 0; t < 8 - J; ++t)
 #pragma unroll
@@ -436,7 +513,8 @@ __device__ __forceinline__ void tile_factor_publish(d4 (&T)[NT], double* __restr
 #pragma unroll
   for (int t = 1; t < 8 - J; ++t)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) lp[(16 * (J + t) + lk + 4 * r) * kLpStride + lr] = T[t][r];
+    for (int r = 0; r < 4; ++r)
+      lp[(16 * (J + t) + tile_row(lk, r)) * kLpStride + lr] = T[t][r];
 }
 
 // Rank-16 update of this wave's tiles (K + t, K), t < 8 - K, of tile column
@@ -447,11 +525,12 @@ __device__ __forceinline__ void tile_apply(d4 (&T)[NT], const double* __restrict
   double b[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) b[s] = lp[(16 * K + lr) * kLpStride + 4 * s + lk];
+  const int ar = mfma_row(lr);
 #pragma unroll
   for (int t = 0; t < 8 - K; ++t) {
     double a[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) a[s] = -lp[(16 * (K + t) + lr) * kLpStride + 4 * s + lk];
+    for (int s = 0; s < 4; ++s) a[s] = -lp[(16 * (K + t) + ar) * kLpStride + 4 * s + lk];
 #pragma unroll
     for (int s = 0; s < 4; ++s) T[t] = mfma(a[s], b[s], T[t]);
   }
@@ -510,40 +589,75 @@ __device__ __forceinline__ void tile_steps(d4 (&T0)[8], d4 (&T1)[4], double* lp,
    ...);
 }
 
-// Tiles (K + t, K), t < NT, of tile column K between global memory and T
-// (rows and columns past nb padded with the identity on load; the diagonal
-// tile whole, its upper part mirrored from the lower one).
+// Tiles (K + t, K), t < NT, of tile column K from global memory into T,
+// rows and columns past nb padded with the identity.  The diagonal tile is
+// read whole, its upper part mirrored from the lower one; whole tiles below
+// it are read as row pairs (16-byte loads, when ld is even).
 template <int NT>
 __device__ __forceinline__ void tile_load(d4 (&T)[NT], int K, const double* __restrict__ Akk,
                                           int64_t ld, int nb, int lr, int lk) {
+  const int col = 16 * K + lr;
+  const bool pairs = (ld & 1) == 0;
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+  for (int t = 0; t < NT; ++t) {
+    const int r0 = 16 * (K + t);
+    if (t > 0 && pairs && r0 + 16 <= nb && 16 * K + 16 <= nb) {
+      if (t < 8 - K) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * (K + t) + lk + 4 * r, col = 16 * K + lr;
-      // the diagonal tile's upper part mirrors the lower one
-      const bool live = (t < 8 - K) && row < nb && col < nb;
-      const int64_t off = (row >= col) ? (int64_t)col * ld + row : (int64_t)row * ld + col;
-      double v = (row == col) ? 1.0 : 0.0;
-      if (live) v = Akk[off];
-      T[t][r] = v;
+        for (int h = 0; h < 2; ++h) {
+          const double2 v = *reinterpret_cast<const double2*>(
+              Akk + (int64_t)col * ld + r0 + tile_row(lk, 2 * h));
+          T[t][2 * h] = v.x;
+          T[t][2 * h + 1] = v.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + tile_row(lk, r);
+        const bool live = (t < 8 - K) && row < nb && col < nb;
+        const int64_t off = (row >= col) ? (int64_t)col * ld + row : (int64_t)row * ld + col;
+        double v = (row == col) ? 1.0 : 0.0;
+        if (live) v = Akk[off];
+        T[t][r] = v;
+      }
     }
+  }
 }
 
+// Tiles of tile column K back to global memory (lower triangle, rows and
+// columns below nb; whole tiles below the diagonal as row pairs) and into
+// the diagonal 32 x 32 blocks Ld.
 template <int NT>
 __device__ __forceinline__ void tile_store(const d4 (&T)[NT], int K, double* __restrict__ Akk,
                                            int64_t ld, int nb, double* __restrict__ Ld, int lr,
                                            int lk) {
+  const int col = 16 * K + lr;
+  const bool pairs = (ld & 1) == 0;
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+  for (int t = 0; t < NT; ++t) {
+    const int I = K + t, r0 = 16 * I;
+    if (t < 8 - K) {
+      if (t > 0 && pairs && r0 + 16 <= nb && 16 * K + 16 <= nb) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int I = K + t, row = 16 * I + lk + 4 * r, col = 16 * K + lr;
-      if (t < 8 - K && row >= col) {
-        if (row < nb && col < nb) Akk[(int64_t)col * ld + row] = T[t][r];
-        if ((I >> 1) == (K >> 1)) Ld[(row >> 5) * SBB + (col & 31) * SB + (row & 31)] = T[t][r];
+        for (int h = 0; h < 2; ++h)
+          *reinterpret_cast<double2*>(Akk + (int64_t)col * ld + r0 + tile_row(lk, 2 * h)) =
+              double2{T[t][2 * h], T[t][2 * h + 1]};
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + tile_row(lk, r);
+          if (row >= col && row < nb && col < nb) Akk[(int64_t)col * ld + row] = T[t][r];
+        }
       }
+      if ((I >> 1) == (K >> 1))
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + tile_row(lk, r);
+          if (row >= col) Ld[(row >> 5) * SBB + (col & 31) * SB + (row & 31)] = T[t][r];
+        }
     }
+  }
 }
 
 __global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A, int64_t ld,
@@ -568,7 +682,10 @@ __global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A,
   tile_store(T0, w, Akk, ld, nb, Ld, lr, lk);
   tile_store(T1, w + 4, Akk, ld, nb, Ld, lr, lk);
   if (lane == 0 && bad >= 0) atomicMin(&first_bad, bad);
-  __syncthreads();
+  // LDS only: the global stores of L drain during the inversion
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
   if (tid == 0 && first_bad < NB && st->potrf_info == 0) {
     st->potrf_info = k + first_bad + 1;
     st->status = BD_ERR_NOT_SPD;

@@ -48,6 +48,9 @@ inline void __threadfence() {}
 #define __builtin_amdgcn_mov_dpp(v, ctrl, rm, bm, bc) (v)
 #define __builtin_amdgcn_readfirstlane(v) (v)
 typedef unsigned emu_u32x2 __attribute__((ext_vector_type(2)));
+struct double2 {
+  double x, y;
+};
 inline emu_u32x2 __builtin_amdgcn_permlane16_swap(unsigned a, unsigned b, bool, bool) { return emu_u32x2{a, b}; }
 inline emu_u32x2 __builtin_amdgcn_permlane32_swap(unsigned a, unsigned b, bool, bool) { return emu_u32x2{a, b}; }
 inline int atomicMin(int* p, int v) { const int o = *p; if (v < o) *p = v; return o; }
@@ -58,6 +61,7 @@ inline int atomicMin(int* p, int v) { const int o = *p; if (v < o) *p = v; retur
 #define __builtin_amdgcn_fence(...) ((void)0)
 #define __builtin_amdgcn_wave_barrier() ((void)0)
 #define __builtin_amdgcn_sched_barrier(m) ((void)0)
+#define __builtin_amdgcn_s_barrier() ((void)0)
 template <typename T> inline T __shfl_xor(T v, int, int = 64) { return v; }
 extern long g_emu_launches;
 // Optional observer of every launch: kernel address, grid, and the
