@@ -37,15 +37,22 @@ def chol_flops(n: int) -> float:
     return n**3 / 3.0 + n**2 / 2.0 + n / 6.0
 
 
-def syrk_launches(n: int, nb: int = 128, step_panels: int = 2,
+def step_width(n: int, k0: int, nb: int, max_panels: int, wide_rows: int) -> int:
+    """Columns of the factorisation step starting at column k0: up to
+    max_panels panels while more than wide_rows rows remain, two after."""
+    panels = max_panels if n - k0 > wide_rows else min(max_panels, 2)
+    return min(panels * nb, n - k0)
+
+
+def syrk_launches(n: int, nb: int = 128, max_panels: int = 4, wide_rows: int = 4096,
                   lookahead: bool = True) -> list[tuple]:
     """Every trailing-update launch of one factorisation in the library's
-    schedule (steps of `step_panels` panels with lookahead): per launch
-    (flops, lower elements updated, operand rows, kdim, kind) with flops = 2
-    per multiply-add over the lower elements of the tiles it updates; kind
-    "next" for the columns of the next step (the lookahead chain, kernel
-    syrk_next_*), "bulk" for the rest (kernel syrk_update_*)."""
-    step = step_panels * nb
+    schedule (steps of up to `max_panels` panels, see step_width, with
+    lookahead): per launch (flops, lower elements updated, operand rows,
+    kdim, kind) with flops = 2 per multiply-add over the lower elements of
+    the tiles it updates; kind "next" for the columns of the next step (the
+    lookahead chain, kernel syrk_next_*), "bulk" for the rest (kernel
+    syrk_update_*)."""
     out = []
 
     def trailing(r0, kdim, tiles, nnext):
@@ -70,14 +77,16 @@ def syrk_launches(n: int, nb: int = 128, step_panels: int = 2,
             out.append((2.0 * elems * kdim, float(elems), rows, kdim,
                         "next" if tiles == "next" else "bulk"))
 
+    def width(k0):
+        return step_width(n, k0, nb, max_panels, wide_rows)
+
     def factor_step(k0):
-        kp, p = k0, 0
-        while p < step_panels and kp < n:
-            if p > 0:
+        kp, end = k0, k0 + width(k0)
+        while kp < end:
+            if kp > k0:
                 trailing(kp, kp - k0, "next", 1)
-            p += 1
             kp += nb
-        return kp - k0
+        return end - k0
 
     if not lookahead:
         k = 0
@@ -90,9 +99,10 @@ def syrk_launches(n: int, nb: int = 128, step_panels: int = 2,
     w, k = factor_step(0), 0
     while k + w < n:
         r0 = k + w
-        trailing(r0, w, "next", step // nb)
+        nnext = -(-width(r0) // nb)
+        trailing(r0, w, "next", nnext)
         wn = factor_step(r0)
-        trailing(r0, w, "rest", step // nb)
+        trailing(r0, w, "rest", nnext)
         k, w = r0, wn
     return out
 
@@ -102,9 +112,12 @@ def syrk_per_launch(n: int, esize: int, kind: str = "bulk") -> tuple[float, floa
     one kind, and the launch count, of one factorisation.  Bytes: each
     updated lower element of C read and written once in FP64 (16 B) plus
     each operand row of L read once (kdim values of `esize` bytes)."""
-    sp = 1 if os.environ.get("BDRPY_STEP_PANELS", "").startswith("1") else 2
+    sp = os.environ.get("BDRPY_STEP_PANELS", "")
+    mp = 1 if sp.startswith("1") else 2 if sp.startswith("2") else 4
+    wide = int(os.environ.get("BDRPY_WIDE_ROWS", "4096"))
     la = not os.environ.get("BDRPY_LOOKAHEAD", "").startswith("0")
-    ls = [x for x in syrk_launches(n, step_panels=sp, lookahead=la) if x[4] == kind]
+    ls = [x for x in syrk_launches(n, max_panels=mp, wide_rows=wide, lookahead=la)
+          if x[4] == kind]
     fl = sum(x[0] for x in ls)
     by = sum(16.0 * x[1] + x[2] * x[3] * esize for x in ls)
     return fl / len(ls), by / len(ls), len(ls)

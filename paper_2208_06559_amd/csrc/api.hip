@@ -27,7 +27,8 @@ struct bd_handle_s {
   int pairs_hint;      // D products the last tension solve needed
   hipStream_t aux;     // lookahead stream of the Cholesky (default priority)
   hipEvent_t ev[4];    // fork / panel-ready / rest-done / next-columns-done events
-  int step_panels;     // Cholesky panels applied per pass over the trailing matrix
+  int step_panels;     // most Cholesky panels applied per pass over the trailing matrix
+  int64_t wide_rows;   // steps of more than two panels while more rows than this remain
   bool tile_potrf;     // Cholesky diagonal blocks on matrix cores
 };
 
@@ -153,10 +154,15 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   h->pairs_hint = 0;
   h->aux = nullptr;
   h->ev[0] = h->ev[1] = h->ev[2] = h->ev[3] = nullptr;
-  // BDRPY_STEP_PANELS=1 applies one panel per trailing pass (for
-  // comparisons); by default two panels share each pass over the matrix.
+  // BDRPY_STEP_PANELS=1 or 2 caps the panels per trailing pass (for
+  // comparisons).  By default four panels share each pass while the
+  // trailing matrix is large (more than BDRPY_WIDE_ROWS rows, default 4096),
+  // halving its HBM traffic per flop, and two once the lookahead chain of
+  // diagonal factors and panel solves is the longer path.
   const char* sp = getenv("BDRPY_STEP_PANELS");
-  h->step_panels = (sp && sp[0] == '1') ? 1 : 2;
+  h->step_panels = (sp && sp[0] == '1') ? 1 : (sp && sp[0] == '2') ? 2 : 4;
+  const char* wr = getenv("BDRPY_WIDE_ROWS");
+  h->wide_rows = wr ? atoll(wr) : 4096;
   // BDRPY_POTRF=reg factors the diagonal blocks with the register-tiled
   // kernel (for comparisons); by default they run on matrix cores.
   const char* pt = getenv("BDRPY_POTRF");
@@ -240,7 +246,7 @@ bd_status_t bd_cholesky(bd_handle_t h, int64_t n, double* d_A, int64_t ld, bd_pr
   if (ws_bytes < bd::cholesky_workspace_bytes(n, prec)) return BD_ERR_PARAM;
   if (reset(h) != hipSuccess) return BD_ERR_HIP;
   return hip_status(bd::launch_cholesky(h->stream, h->aux, h->ev, n, d_A, ld, prec, d_ws, h->st,
-                                              h->step_panels, h->tile_potrf));
+                                              h->step_panels, h->wide_rows, h->tile_potrf));
 }
 
 bd_status_t bd_brownian(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_L,
@@ -288,7 +294,7 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
   if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
   if (he == hipSuccess)
     he = bd::launch_cholesky(s, h->aux, h->ev, n, D, ld, prec, base + L.chol, h->st,
-                              h->step_panels, h->tile_potrf);
+                              h->step_panels, h->wide_rows, h->tile_potrf);
   if (he == hipSuccess)
     he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);

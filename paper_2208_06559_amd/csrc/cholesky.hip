@@ -947,13 +947,31 @@ struct CholCtx {
   // MIXED: FP32 copies of the panels of consecutive steps, n x kMaxStep each,
   // indexed by global row (P[c * n + row]); null in FP64
   float* P32[2];
-  int step;  // columns per step: 1 or 2 panels
-  bool tile_potrf;  // diagonal blocks on matrix cores (else register tiles)
+  int max_panels;     // panels per step: 1, 2 or 4
+  int64_t wide_rows;  // four-panel steps only while more rows than this remain
+  bool tile_potrf;    // diagonal blocks on matrix cores (else register tiles)
   DevState* st;
 };
 
+// Columns of the factorisation step starting at column k0: wide steps
+// while the trailing matrix is large (its update dominates), narrower ones
+// once the chain of diagonal factors is the longer path.
+int64_t step_width(const CholCtx& c, int64_t k0) {
+  const int panels = (c.n - k0 > c.wide_rows) ? c.max_panels
+                                              : (c.max_panels < 2 ? c.max_panels : 2);
+  return (c.n - k0 < (int64_t)panels * NB) ? c.n - k0 : (int64_t)panels * NB;
+}
+
+// Steps before the one starting at k0; consecutive steps use the two FP32
+// panel copies in turn.
+int64_t step_index(const CholCtx& c, int64_t k0) {
+  int64_t i = 0;
+  for (int64_t k = 0; k < k0; k += step_width(c, k)) ++i;
+  return i;
+}
+
 float* step_copy(const CholCtx& c, int64_t k0) {
-  return c.P32[0] ? c.P32[(k0 / c.step) & 1] : nullptr;
+  return c.P32[0] ? c.P32[step_index(c, k0) & 1] : nullptr;
 }
 
 // Diagonal block and panel solve of the panel at column kp, which is panel
@@ -1019,12 +1037,13 @@ hipError_t trailing(const CholCtx& c, hipStream_t s, int64_t k0, int64_t r0, int
 hipError_t factor_step(const CholCtx& c, hipStream_t s, int64_t k0, int64_t* width) {
   int64_t kp = k0;
   hipError_t e;
-  for (int p = 0; p < c.step / NB && kp < c.n; ++p, kp += NB) {
+  const int64_t end = k0 + step_width(c, k0);
+  for (int p = 0; kp < end; ++p, kp += NB) {
     if (p > 0 && (e = trailing(c, s, k0, kp, (int)(kp - k0), kTilesNext, 1)) != hipSuccess)
       return e;
     if ((e = factor_panel(c, s, k0, kp)) != hipSuccess) return e;
   }
-  *width = kp - k0;
+  *width = end - k0;
   return hipSuccess;
 }
 
@@ -1039,14 +1058,15 @@ hipError_t factor_step(const CholCtx& c, hipStream_t s, int64_t k0, int64_t* wid
 // aux == nullptr everything runs on `s` in order.
 hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int64_t n, double* A,
                            int64_t ld, bd_precision_t prec, void* ws, DevState* st,
-                           int step_panels, bool tile_potrf) {
+                           int max_panels, int64_t wide_rows, bool tile_potrf) {
   CholCtx c;
   c.n = n;
   c.ld = ld;
   c.A = A;
   c.st = st;
   c.W = static_cast<double*>(ws);
-  c.step = (step_panels == 2 ? 2 : 1) * NB;
+  c.max_panels = (max_panels >= 4) ? 4 : (max_panels == 2 ? 2 : 1);
+  c.wide_rows = wide_rows;
   c.tile_potrf = tile_potrf;
   c.P32[0] = c.P32[1] = nullptr;
   if (prec == BD_PREC_MIXED) {
@@ -1054,7 +1074,6 @@ hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int
     c.P32[0] = reinterpret_cast<float*>(p);
     c.P32[1] = reinterpret_cast<float*>(p + align_up(sizeof(float) * (size_t)n * kMaxStep, 256));
   }
-  const int nnext = c.step / NB;
   hipError_t e;
   int64_t w = 0;
   if (!aux) {
@@ -1071,6 +1090,7 @@ hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int
   if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
   for (int64_t k = 0; k + w < n;) {
     const int64_t r0 = k + w;
+    const int nnext = (int)((step_width(c, r0) + NB - 1) / NB);  // panels of the next step
     // main: step k must be factored before it is applied
     if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
     // aux: the next step's tile columns must have every earlier update

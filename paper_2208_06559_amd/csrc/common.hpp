@@ -30,7 +30,7 @@ constexpr int kWave = 64;
 // Cholesky blocking: trailing-update block (panel width) and MFMA tile.
 constexpr int kNB = 128;       // panel width
 constexpr int kTile = 128;     // trailing-update workgroup tile (square)
-constexpr int kMaxStep = 2 * kNB;  // widest factorisation step (two panels)
+constexpr int kMaxStep = 4 * kNB;  // widest factorisation step (four panels)
 
 // ---------------------------------------------------------------- launchers
 // rpy.hip
@@ -41,7 +41,7 @@ hipError_t launch_rpy_assemble(hipStream_t s, const bd_params_t& p, const double
 size_t cholesky_workspace_bytes(int64_t n, bd_precision_t prec);
 hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int64_t n, double* A,
                            int64_t ld, bd_precision_t prec, void* ws, DevState* st,
-                           int step_panels, bool tile_potrf);
+                           int max_panels, int64_t wide_rows, bool tile_potrf);
 
 // brownian.hip
 size_t brownian_workspace_bytes(int64_t n);

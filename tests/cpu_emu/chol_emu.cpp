@@ -6,8 +6,9 @@
 // order, each exactly once, before its diagonal block is factored (tracked
 // on 64 x 64 sub-tiles, the finest tile a launch uses), and
 // every diagonal block is factored exactly once.
-// Usage: chol_emu n ld prec(0 fp64, 1 mixed) step_panels(1|2) lookahead(0|1)
-//        [tile_potrf(0|1), default 1]
+// Usage: chol_emu n ld prec(0 fp64, 1 mixed) max_panels(1|2|4) lookahead(0|1)
+//        [tile_potrf(0|1), default 1] [wide_rows, default 0: every step as
+//        wide as max_panels allows]
 #include <map>
 #include <utility>
 
@@ -88,10 +89,11 @@ void observe(const void* kernel, dim3 grid, const int64_t* a, int nargs) {
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc != 6 && argc != 7) return 2;
+  if (argc < 6 || argc > 8) return 2;
   const int64_t n = atoll(argv[1]), ld = atoll(argv[2]);
   const int prec = atoi(argv[3]), sp = atoi(argv[4]), use_aux = atoi(argv[5]);
-  const bool tile = argc == 7 ? atoi(argv[6]) != 0 : true;
+  const bool tile = argc >= 7 ? atoi(argv[6]) != 0 : true;
+  const int64_t wide = argc >= 8 ? atoll(argv[7]) : 0;
   double* A = (double*)malloc(sizeof(double) * ((n - 1) * ld + n));
   for (int64_t c = 0; c < n; ++c)
     for (int64_t i = 0; i < n; ++i) A[c * ld + i] = (i == c) ? 1.0 + n : 0.1;
@@ -105,12 +107,12 @@ int main(int argc, char** argv) {
   bd::DevState* st = (bd::DevState*)calloc(1, sizeof(bd::DevState));
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   const hipError_t e = bd::launch_cholesky(nullptr, use_aux ? (hipStream_t)0x1 : nullptr, ev, n, A,
-                                           ld, (bd_precision_t)prec, ws, st, sp, tile);
+                                           ld, (bd_precision_t)prec, ws, st, sp, wide, tile);
   if (prec == 0)
     for (int64_t J = 0; J * bd::NB < n; ++J)
       if (g_factored[J] != 1) fail("diagonal block not factored once", J, g_factored[J], 0);
-  printf("n=%lld ld=%lld prec=%d step_panels=%d lookahead=%d tile_potrf=%d: status %d, %ld launches, %d schedule errors\n",
-         (long long)n, (long long)ld, prec, sp, use_aux, (int)tile, e, g_emu_launches, g_errors);
+  printf("n=%lld ld=%lld prec=%d max_panels=%d lookahead=%d tile_potrf=%d wide_rows=%lld: status %d, %ld launches, %d schedule errors\n",
+         (long long)n, (long long)ld, prec, sp, use_aux, (int)tile, (long long)wide, e, g_emu_launches, g_errors);
   free(A);
   free(ws);
   free(st);

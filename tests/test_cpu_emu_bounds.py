@@ -46,13 +46,15 @@ CASES = [(n, ld_pad) for n in (1, 6, 127, 128, 129, 256, 257, 383, 640, 1101, 30
 @pytest.mark.parametrize("n,ld_pad", CASES)
 @pytest.mark.parametrize("prec", [0, 1])
 def test_cholesky_accesses_in_bounds(emu, n, ld_pad, prec):
-    # every schedule with the matrix-core diagonal-block kernel, and the
+    # every step width (1, 2 or 4 panels, and 4 turning to 2 halfway) with
+    # and without lookahead on the matrix-core diagonal-block kernel, and the
     # default schedule with the register-tiled one
-    runs = [(sp, la, 1) for sp in (1, 2) for la in (0, 1)] + [(2, 1, 0)]
-    for sp, la, tile in runs:
-        r = subprocess.run([emu, str(n), str(n + ld_pad), str(prec), str(sp), str(la), str(tile)],
-                           capture_output=True, text=True, timeout=300)
-        assert r.returncode == 0, (n, ld_pad, prec, sp, la, tile, r.stderr[-3000:])
+    runs = [(sp, la, 1, 0) for sp in (1, 2, 4) for la in (0, 1)]
+    runs += [(4, la, 1, n // 2) for la in (0, 1)] + [(4, 1, 0, n // 2)]
+    for sp, la, tile, wide in runs:
+        r = subprocess.run([emu, str(n), str(n + ld_pad), str(prec), str(sp), str(la), str(tile),
+                            str(wide)], capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, (n, ld_pad, prec, sp, la, tile, wide, r.stderr[-3000:])
         assert "status 0" in r.stdout and " 0 schedule errors" in r.stdout
 
 

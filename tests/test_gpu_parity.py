@@ -105,17 +105,20 @@ def test_cholesky_mixed_residual(h, N, seed):
     assert np.all(np.diag(L) > 0)
 
 
-@pytest.mark.parametrize("step_panels", ["1", "2"])
+# (most panels per trailing pass, rows below which steps narrow to two
+# panels): one, two or four panels throughout, and four turning to two
+@pytest.mark.parametrize("steps", [("1", "0"), ("2", "0"), ("4", "0"), ("4", "600")])
 @pytest.mark.parametrize("lookahead", ["0", "1"])
 @pytest.mark.parametrize("prec", [B.PREC_FP64, B.PREC_MIXED])
 @pytest.mark.parametrize("potrf", ["tile", "reg"])
-def test_cholesky_schedules(monkeypatch, step_panels, lookahead, prec, potrf):
-    """Every factorisation schedule (one or two panels per trailing pass,
-    with or without the lookahead stream, diagonal blocks on matrix cores or
-    in register tiles) on a ragged n spanning several steps: FP64 to the
-    rounding level of the oracle's factor, MIXED through its residual
-    bound."""
-    monkeypatch.setenv("BDRPY_STEP_PANELS", step_panels)
+def test_cholesky_schedules(monkeypatch, steps, lookahead, prec, potrf):
+    """Every factorisation schedule (one, two or four panels per trailing
+    pass, or four turning to two, with or without the lookahead stream,
+    diagonal blocks on matrix cores or in register tiles) on a ragged n
+    spanning several steps: FP64 to the rounding level of the oracle's
+    factor, MIXED through its residual bound."""
+    monkeypatch.setenv("BDRPY_STEP_PANELS", steps[0])
+    monkeypatch.setenv("BDRPY_WIDE_ROWS", steps[1])
     monkeypatch.setenv("BDRPY_LOOKAHEAD", lookahead)
     monkeypatch.setenv("BDRPY_POTRF", potrf)
     hh = B.Handle(0)
