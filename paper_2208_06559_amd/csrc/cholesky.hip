@@ -664,10 +664,14 @@ __global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A,
                                                           int64_t k, int nb,
                                                           double* __restrict__ W,
                                                           DevState* __restrict__ st) {
-  __shared__ double lp[2 * NB * kLpStride];  // published column blocks (double buffer)
-  __shared__ double Ld[NSB * SBB];           // diagonal 32 x 32 blocks of L, column-major
-  __shared__ double rdg[NB];                 // 1 / L(j,j)
-  __shared__ int first_bad;                  // first non-positive pivot (NB: none)
+  // published column blocks (double buffer); after the last of them has
+  // been applied, the diagonal 32 x 32 blocks of L (column-major) for the
+  // inversion
+  __shared__ double lp[2 * NB * kLpStride];
+  static_assert(2 * NB * kLpStride >= NSB * SBB, "diagonal blocks fit the publish buffers");
+  double* const Ld = lp;
+  __shared__ double rdg[NB];  // 1 / L(j,j)
+  __shared__ int first_bad;   // first non-positive pivot (NB: none)
   const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   double* Akk = A + k * ld + k;
@@ -778,9 +782,13 @@ __global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
 // 3. Trailing update C -= L L^T on the lower TS x TS tiles (TS = 128, or 64
 //    for the columns on the lookahead chain) of the m x m trailing matrix; L
 //    is m x kdim (column-major, ldl) in FP64 or FP32, kdim a multiple of KC
-//    (one or two panels).  Four waves, each a TS/2 x TS/2 quadrant (the
+//    (one to four panels).  Four waves, each a TS/2 x TS/2 quadrant (the
 //    strictly upper quadrant of a diagonal tile is skipped).  Operands are
-//    staged through double-buffered LDS in K-chunks of KC.
+//    staged through double-buffered LDS in K-chunks of KC, each row's KC
+//    values contiguous (rows 144 bytes apart: 16-byte accesses by 16
+//    consecutive rows meet every bank once).  Lane (lr, lk) of an MFMA takes
+//    k = (KC/4) lk + kq at step kq (one K order for both operands), so its
+//    operands for a whole chunk are one 32-byte run per 16 x 16 block.
 // ------------------------------------------------------------------------
 template <typename T>
 struct SyrkCfg;
@@ -795,7 +803,9 @@ struct SyrkCfg<float> {
   typedef f4 acc_t;
 };
 
-constexpr int kPad = 4;
+// LDS row of a staged operand chunk: KC values plus 16 bytes of padding
+template <typename T>
+constexpr int lds_row() { return SyrkCfg<T>::KC + 16 / (int)sizeof(T); }
 
 // Tile sets of one trailing update: every lower tile, only the first nnext
 // tile columns (the next step's panels, updated ahead), or every lower tile
@@ -817,8 +827,11 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
   constexpr int NBK = WT / 16;         // 16 x 16 MFMA blocks per quadrant side
   constexpr int NLD = KC * TS / 256;   // elements per thread per operand per chunk
   static_assert(TS == 64 || TS == 128, "tile size");
-  __shared__ T As[2][KC][TS + kPad];  // row side
-  __shared__ T Bs[2][KC][TS + kPad];  // column side
+  constexpr int LR = lds_row<T>();
+  constexpr int KQ = KC / 4;  // MFMA steps per chunk; each lane's run of k values
+  static_assert(KQ * sizeof(T) == 32 && NLD * sizeof(T) % 16 == 0, "32-byte runs");
+  __shared__ __attribute__((aligned(16))) T As[2][TS][LR];  // row side, [row][k]
+  __shared__ __attribute__((aligned(16))) T Bs[2][TS][LR];  // column side
 
   // XCD x receives workgroups x, x+8, ...: cnt(x) = base + (x < rem) of them;
   // the q-th of them takes tile x*base + min(x, rem) + q (a bijection).
@@ -855,26 +868,33 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[bj][bi][r] = 0;
 
+  // thread: operand row gr, chunk columns gk .. gk + NLD - 1 (consecutive
+  // lanes read consecutive rows of one column)
+  const int gr = tid % TS, gk = (tid / TS) * NLD;
+  // rows past m are clamped (their products only reach masked outputs)
+  const int64_t ia = (row0 + gr < m) ? row0 + gr : m - 1;
+  const int64_t ib = (col0 + gr < m) ? col0 + gr : m - 1;
   T ra[NLD], rb[NLD];
   auto gload = [&](int kk) {
 #pragma unroll
     for (int q = 0; q < NLD; ++q) {
-      const int e = tid + 256 * q;
-      const int kc = e / TS, r = e % TS;
-      // rows past m are clamped (their products only reach masked outputs)
-      const int64_t ia = (row0 + r < m) ? row0 + r : m - 1;
-      const int64_t ib = (col0 + r < m) ? col0 + r : m - 1;
-      ra[q] = L[(int64_t)(kk + kc) * ldl + ia];
-      rb[q] = L[(int64_t)(kk + kc) * ldl + ib];
+      ra[q] = L[(int64_t)(kk + gk + q) * ldl + ia];
+      rb[q] = L[(int64_t)(kk + gk + q) * ldl + ib];
     }
   };
+  typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int V = 16 / (int)sizeof(T);  // values per 16-byte access
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-      const int e = tid + 256 * q;
-      const int kc = e / TS, r = e % TS;
-      As[buf][kc][r] = ra[q];
-      Bs[buf][kc][r] = rb[q];
+    for (int q = 0; q < NLD; q += V) {
+      v16 a, b;
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        a[u] = ra[q + u];
+        b[u] = rb[q + u];
+      }
+      *reinterpret_cast<v16*>(&As[buf][gr][gk + q]) = a;
+      *reinterpret_cast<v16*>(&Bs[buf][gr][gk + q]) = b;
     }
   };
 
@@ -886,18 +906,29 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
   for (int ch = 0; ch < nch; ++ch) {
     const int buf = ch & 1;
     if (active) {
+      T af[NBK][KQ], bf[NBK][KQ];
 #pragma unroll
-      for (int kq = 0; kq < KC / 4; ++kq) {
-        T af[NBK], bf[NBK];
+      for (int bj = 0; bj < NBK; ++bj)
 #pragma unroll
-        for (int bj = 0; bj < NBK; ++bj) af[bj] = Bs[buf][4 * kq + lk][WT * wc + 16 * bj + lr];
+        for (int h = 0; h < KQ; h += V) {
+          const v16 x = *reinterpret_cast<const v16*>(&Bs[buf][WT * wc + 16 * bj + lr][KQ * lk + h]);
 #pragma unroll
-        for (int bi = 0; bi < NBK; ++bi) bf[bi] = As[buf][4 * kq + lk][WT * wr + 16 * bi + lr];
+          for (int u = 0; u < V; ++u) af[bj][h + u] = x[u];
+        }
+#pragma unroll
+      for (int bi = 0; bi < NBK; ++bi)
+#pragma unroll
+        for (int h = 0; h < KQ; h += V) {
+          const v16 x = *reinterpret_cast<const v16*>(&As[buf][WT * wr + 16 * bi + lr][KQ * lk + h]);
+#pragma unroll
+          for (int u = 0; u < V; ++u) bf[bi][h + u] = x[u];
+        }
+#pragma unroll
+      for (int kq = 0; kq < KQ; ++kq)
 #pragma unroll
         for (int bj = 0; bj < NBK; ++bj)
 #pragma unroll
-          for (int bi = 0; bi < NBK; ++bi) acc[bj][bi] = mfma(af[bj], bf[bi], acc[bj][bi]);
-      }
+          for (int bi = 0; bi < NBK; ++bi) acc[bj][bi] = mfma(af[bj][kq], bf[bi][kq], acc[bj][bi]);
     }
     if (ch + 1 < nch) {
       sstore(buf ^ 1);                       // chunk ch+1, loaded one iteration ago
