@@ -36,12 +36,39 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int NB = kNB;       // panel width
 constexpr int kTS = kTile;    // trailing-update tile
 
-__device__ __forceinline__ void tri_index(int t, int& r, int& c) {
-  int rr = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while ((rr + 1) * (rr + 2) / 2 <= t) ++rr;
-  while (rr * (rr + 1) / 2 > t) --rr;
-  r = rr;
-  c = t - rr * (rr + 1) / 2;
+// Lower tile (ti, tj) number t of an mt x mt tile triangle in banded order:
+// bands of kBand tile rows; within a band, column by column, first the
+// band's rows left of its diagonal block, then that block's lower triangle.
+// An XCD's run of consecutive tiles then touches kBand row panels and a
+// window of column panels, which its L2 can hold, where the row-major
+// order touches every column panel up to the current row.
+constexpr int kBand = 8;
+__host__ __device__ __forceinline__ int64_t band_start(int I) {  // tiles before band I (full bands)
+  return (int64_t)kBand * kBand * I * (I - 1) / 2 + (int64_t)I * kBand * (kBand + 1) / 2;
+}
+__host__ __device__ __forceinline__ void band_index(int t, int mt, int& ti, int& tj) {
+  const double a = kBand * kBand * 0.5, b = kBand * (kBand + 1) * 0.5 - a;  // start = a I^2 + b I
+  int I = (int)((-b + sqrt(b * b + 4.0 * a * (double)t)) / (2.0 * a));
+  const int last = (mt - 1) / kBand;
+  if (I > last) I = last;
+  while (I > 0 && band_start(I) > t) --I;
+  while (I < last && band_start(I + 1) <= t) ++I;
+  int o = (int)(t - band_start(I));
+  const int rows = (mt - kBand * I < kBand) ? mt - kBand * I : kBand;
+  const int rect = kBand * I * rows;
+  if (o < rect) {
+    tj = o / rows;
+    ti = kBand * I + o % rows;
+  } else {
+    o -= rect;
+    int c = 0;
+    while (o >= rows - c) {
+      o -= rows - c;
+      ++c;
+    }
+    tj = kBand * I + c;
+    ti = tj + o;
+  }
 }
 
 __host__ __device__ __forceinline__ int xcd_contiguous(int t, int nwg) {
@@ -848,7 +875,8 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
     ti = q + r;
     tj = q;
   } else {
-    tri_index(t, ti, tj);
+    const int mt = (int)((m + TS - 1) / TS) - (tiles == kTilesRest ? nnext : 0);
+    band_index(t, mt, ti, tj);
     if (tiles == kTilesRest) {
       ti += nnext;
       tj += nnext;

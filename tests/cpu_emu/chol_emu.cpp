@@ -56,7 +56,7 @@ void observe(const void* kernel, dim3 grid, const int64_t* a, int nargs) {
         tj = q;
       } else {
         int rr, cc;
-        tri_index((int)t, rr, cc);
+        band_index((int)t, (int)(mt - (tiles == kTilesRest ? nnext : 0)), rr, cc);
         ti = rr;
         tj = cc;
         if (tiles == kTilesRest) {
