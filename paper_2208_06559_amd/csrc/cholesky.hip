@@ -699,6 +699,9 @@ __global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A,
   double* const Ld = lp;
   __shared__ double rdg[NB];  // 1 / L(j,j)
   __shared__ int first_bad;   // first non-positive pivot (NB: none)
+  // the block is on the critical path of the factorisation: its waves take
+  // issue priority over trailing-update waves sharing their SIMDs
+  __builtin_amdgcn_s_setprio(3);
   const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   double* Akk = A + k * ld + k;
@@ -778,6 +781,7 @@ __global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
     double* __restrict__ A, int64_t ld, int64_t k, int nb, int64_t m, const double* __restrict__ W,
     float* __restrict__ P32, int64_t ldp) {
   static_assert(NSB == 4 && res_row_f64_is_lk_plus_4r, "register layout of the panel solve");
+  __builtin_amdgcn_s_setprio(3);  // critical path, like the diagonal block
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   const int64_t row = (int64_t)blockIdx.x * kRB + 16 * w + lr;
@@ -854,6 +858,7 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
   constexpr int NBK = WT / 16;         // 16 x 16 MFMA blocks per quadrant side
   constexpr int NLD = KC * TS / 256;   // elements per thread per operand per chunk
   static_assert(TS == 64 || TS == 128, "tile size");
+  if constexpr (TS == 64) __builtin_amdgcn_s_setprio(3);  // the lookahead chain's updates
   constexpr int LR = lds_row<T>();
   constexpr int KQ = KC / 4;  // MFMA steps per chunk; each lane's run of k values
   static_assert(KQ * sizeof(T) == 32 && NLD * sizeof(T) % 16 == 0, "32-byte runs");

@@ -62,6 +62,7 @@ inline int atomicMin(int* p, int v) { const int o = *p; if (v < o) *p = v; retur
 #define __builtin_amdgcn_wave_barrier() ((void)0)
 #define __builtin_amdgcn_sched_barrier(m) ((void)0)
 #define __builtin_amdgcn_s_barrier() ((void)0)
+#define __builtin_amdgcn_s_setprio(p) ((void)0)
 template <typename T> inline T __shfl_xor(T v, int, int = 64) { return v; }
 extern long g_emu_launches;
 // Optional observer of every launch: kernel address, grid, and the
