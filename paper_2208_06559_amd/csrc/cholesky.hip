@@ -353,6 +353,12 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
 // ------------------------------------------------------------------------
 constexpr int kLpStride = 17;  // padded LDS row of a published column block
 
+// Inline assembly statements keep their program order (volatile); the
+// host build that checks memory accesses defines BD_ASM as a no-op.
+#ifndef BD_ASM
+#define BD_ASM asm volatile
+#endif
+
 __host__ __device__ constexpr int tile_row(int lk, int r) { return 2 * lk + (r & 1) + 8 * (r >> 1); }
 // MFMA row i = lk + 4r of a result tile as a tile row
 __host__ __device__ constexpr int mfma_row(int i) { return tile_row(i & 3, i >> 2); }
@@ -397,16 +403,17 @@ __device__ __forceinline__ double group_bcast(double v) {
 // assembly: a column's writes of an element and the next column's read of
 // it are kept apart by the next pivot's steps (tile 0) or by the next
 // column's tile-0 update and first pivot step (other tiles), scheduling
-// barriers stop the compiler from moving them closer, and the first
+// barriers stop the compiler from moving them closer, the statements are
+// volatile so that they keep their program order, and the first
 // instruction of each column waits for its coefficient.
 template <int C>
 __device__ __forceinline__ void fmac_row_bcast(double& x, double beta, bool wait) {
   if (wait)  // beta may have been written by the instruction before (folded when unrolled)
-    asm("s_nop 1\n\tv_fmac_f64_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+    BD_ASM("s_nop 1\n\tv_fmac_f64_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
         : "+v"(x)
         : "v"(beta), "i"(C));
   else
-    asm("v_fmac_f64_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+    BD_ASM("v_fmac_f64_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
         : "+v"(x)
         : "v"(beta), "i"(C));
 }
@@ -687,6 +694,114 @@ __device__ __forceinline__ void tile_store(const d4 (&T)[NT], int K, double* __r
   }
 }
 
+// x += bcast_C(l) * b, the DPP broadcast on the multiplicand (see
+// fmac_row_bcast for the wait states).
+template <int C>
+__device__ __forceinline__ void fmac_bcast_src(double& x, double l, double b, bool wait) {
+  if (wait)
+    BD_ASM("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(x)
+        : "v"(l), "v"(b), "i"(C));
+  else
+    BD_ASM("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(x)
+        : "v"(l), "v"(b), "i"(C));
+}
+
+// Step K of inverting a lower-triangular 16 x 16 tile L in the tile layout
+// by forward elimination: R (initially I) becomes L^-1.  Row K of the
+// inverse is R(K, .) / L(K,K); every later row i then loses L(i, K) times
+// it.  Lz is L with its diagonal and upper part zeroed, rk = 1 / L(K,K).
+template <int K>
+__device__ __forceinline__ void tile_inv_step(d4& R, const d4& Lz, double rk, int lk, int lr) {
+  constexpr int g = row_group(K), q = row_reg(K);
+  R[q] *= (lk == g) ? rk : 1.0;
+  if constexpr (K < 15) {
+    // -X(K, lr), in every lane group, through the LDS crossbar
+    const double v = R[q];
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int src = 4 * (lr + 16 * g);
+    const uint32_t lo = __builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)(u >> 32));
+    const double xk = -__builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double x = R[r];
+      fmac_bcast_src<K>(x, Lz[r], xk, r == 0);
+      R[r] = x;
+    }
+  }
+}
+
+// Step K of two independent tiles in one scheduling region, so that their
+// dependent chains overlap; the region boundary keeps step K + 1's reads of
+// R at least the other tile's step away from step K's writes.
+template <int... K>
+__device__ __forceinline__ void tile_inv2(d4& R0, const d4& L0, const double (&rd0)[16], d4& R1,
+                                          const d4& L1, const double (&rd1)[16], int lk, int lr,
+                                          std::integer_sequence<int, K...>) {
+  ((tile_inv_step<K>(R0, L0, rd0[K], lk, lr), tile_inv_step<K>(R1, L1, rd1[K], lk, lr),
+    __builtin_amdgcn_sched_barrier(0)),
+   ...);
+}
+
+// Inverses of the four diagonal 32 x 32 blocks of L into W (Winv_p
+// column-major at W + p SBB), from the tiles in registers: wave w inverts
+// its diagonal tiles (w, w) and (w + 4, w + 4) in place of L's in the
+// diagonal blocks Ld; after a barrier wave p forms block p's lower-left
+// part -X_c B X_a (B = L(2p+1, 2p), X_a, X_c the inverses of the diagonal
+// tiles) with two 16 x 16 x 16 MFMA products and writes the whole block.
+__device__ __forceinline__ void invert_diag_tiles(const d4& D0, const d4& D1, double* __restrict__ Ld,
+                                                  const double* __restrict__ rdg,
+                                                  double* __restrict__ W, int w, int lr, int lk) {
+  d4 Lz0, Lz1, R0, R1;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = tile_row(lk, r);
+    Lz0[r] = (row > lr) ? D0[r] : 0.0;
+    Lz1[r] = (row > lr) ? D1[r] : 0.0;
+    R0[r] = R1[r] = (row == lr) ? 1.0 : 0.0;
+  }
+  double rd0[16], rd1[16];  // 1 / L(j,j) of the two tiles, read before the steps
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    rd0[j] = rdg[16 * w + j];
+    rd1[j] = rdg[16 * (w + 4) + j];
+  }
+  tile_inv2(R0, Lz0, rd0, R1, Lz1, rd1, lk, lr, std::make_integer_sequence<int, 16>{});
+  // X tiles over the diagonal tiles of the blocks (columns 16 (K & 1) + lr)
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int K = w + 4 * t, o = 16 * (K & 1);
+    double* Lp = Ld + (K >> 1) * SBB;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Lp[(o + lr) * SB + o + tile_row(lk, r)] = t ? R1[r] : R0[r];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  const double* Lp = Ld + w * SBB;  // block p = w
+  d4 Y = {0, 0, 0, 0}, Z = {0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s)  // Y = B X_a
+    Y = mfma(Lp[(4 * s + lk) * SB + 16 + lr], Lp[lr * SB + 4 * s + lk], Y);
+#pragma unroll
+  for (int s = 0; s < 4; ++s)  // Z = -X_c Y; Y's register s is the B operand of step s
+    Z = mfma(-Lp[(16 + 4 * s + lk) * SB + 16 + lr], Y[s], Z);
+  double* Wp = W + w * SBB;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Wp[lr * SB + 16 + lk + 4 * r] = Z[r];  // rows 16.., columns ..15
+  const int lane = lr + 16 * lk;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {  // the other three quarters, column-major
+    const int qt = i / 4;         // 0: X_a, 1: X_c, 2: upper right (zero)
+    const int e = lane + 64 * (i % 4);
+    const int col = e / 16, row = e % 16;
+    const int oc = (qt == 0) ? 0 : 16, orow = (qt == 1) ? 16 : 0;
+    Wp[(oc + col) * SB + orow + row] = (qt == 2) ? 0.0 : Lp[(oc + col) * SB + orow + row];
+  }
+}
+
 __global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A, int64_t ld,
                                                           int64_t k, int nb,
                                                           double* __restrict__ W,
@@ -724,7 +839,7 @@ __global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A,
     st->potrf_info = k + first_bad + 1;
     st->status = BD_ERR_NOT_SPD;
   }
-  invert_diag_blocks(Ld, rdg, W, tid);
+  invert_diag_tiles(T0[0], T1[0], Ld, rdg, W, w, lr, lk);
 }
 
 // ------------------------------------------------------------------------

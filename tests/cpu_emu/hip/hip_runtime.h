@@ -56,6 +56,7 @@ inline emu_u32x2 __builtin_amdgcn_permlane32_swap(unsigned a, unsigned b, bool, 
 inline int atomicMin(int* p, int v) { const int o = *p; if (v < o) *p = v; return o; }
 // GPU inline assembly has no host meaning: it leaves its operands as they are.
 #define asm(...) ((void)0)
+#define BD_ASM(...) ((void)0)
 #define __builtin_amdgcn_rsq(d) (1.0 / std::sqrt(d))
 #define __builtin_amdgcn_rcp(d) (1.0 / (d))
 #define __builtin_amdgcn_fence(...) ((void)0)
