@@ -214,12 +214,40 @@ __global__ __launch_bounds__(256) void constrain_init_kernel(const double* __res
   }
 }
 
+// Far-field coefficients (R >= 2a) of an RPY block, and 1/R; the same
+// arithmetic as rpy_coeffs_fast.
+__device__ __forceinline__ void rpy_far_coeffs(double R2, const RpyConst& k, double& cI,
+                                               double& cRR, double& y) {
+  y = __builtin_amdgcn_rsq(R2);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double h = 0.5 * R2 * y;
+    y = fma(-h, y, 1.5) * y;
+  }
+  const double inv2 = y * y;
+  const double pre = k.far_pre * y;
+  const double t = k.a2 * inv2;
+  cI = pre * (1.0 + (2.0 / 3.0) * t);
+  cRR = pre * (1.0 - 2.0 * t) * inv2;
+}
+
+// Near-field coefficients (R < 2a) from the same 1/R.
+__device__ __forceinline__ void rpy_near_coeffs(double R2, double y, const RpyConst& k, double& cI,
+                                                double& cRR) {
+  const double R = (R2 > 0.0) ? R2 * y : 0.0;  // coincident beads: the R -> 0 limit
+  cI = k.near_pre * (8.0 / 3.0 - k.near_r * R);
+  cRR = (R2 > 0.0) ? k.near_rr * y : 0.0;
+}
+
 // r = D f.  A workgroup of 16 waves owns kMvI = 16 beads i and sweeps every
 // bead j: lane (il, jp) = (lane % 16, lane / 16) of wave w takes phase
 // 4w + jp, i.e. j = phase, phase + 64, ...; the 64 phase sums of each r_i are
 // then added in a fixed order (no atomics, no cross-workgroup traffic,
 // bitwise reproducible).  16 waves per workgroup keep four waves on each
-// SIMD to hide the FP64 latencies.
+// SIMD to hide the FP64 latencies, and each lane takes two of its beads j
+// per iteration (two independent chains; far-field coefficients straight
+// through, the rare near-field pairs behind a wave-uniform branch), adding
+// them in the same order as one at a time.
 constexpr int kMvThreads = 1024;
 constexpr int kMvWaves = kMvThreads / 64;
 
@@ -228,7 +256,7 @@ __global__ __launch_bounds__(kMvThreads) void dmatvec_kernel(const double* __res
                                                        double* __restrict__ r, int N, RpyConst kc,
                                                        const DevState* __restrict__ st) {
   if (st->done) return;
-  constexpr int kChunk = 512;  // beads j staged in LDS per round
+  constexpr int kChunk = 2048;  // beads j staged in LDS per round (96 KB: one workgroup per CU)
   __shared__ double sx[3 * kChunk], sf[3 * kChunk];
   __shared__ double red[kMvWaves][3][kMvI];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -245,20 +273,44 @@ __global__ __launch_bounds__(kMvThreads) void dmatvec_kernel(const double* __res
       sf[e] = f[3 * j0 + e];
     }
     __syncthreads();
-    for (int jj = 4 * w + jp; jj < nj; jj += 4 * kMvWaves) {
-      const int q = 3 * jj;
-      const double f0 = sf[q], f1 = sf[q + 1], f2 = sf[q + 2];
-      const double R0 = xi0 - sx[q], R1 = xi1 - sx[q + 1], R2c = xi2 - sx[q + 2];
-      double cI, cRR;
-      rpy_coeffs_fast(R0 * R0 + R1 * R1 + R2c * R2c, kc, cI, cRR);
-      if (j0 + jj == ii) {  // D_ii = I
-        cI = 1.0;
-        cRR = 0.0;
+    for (int jj = 4 * w + jp; jj < nj; jj += 8 * kMvWaves) {
+      const int jb = jj + 4 * kMvWaves;
+      const bool hb = jb < nj;
+      const int qa = 3 * jj, qb = 3 * (hb ? jb : jj);
+      const double fa0 = sf[qa], fa1 = sf[qa + 1], fa2 = sf[qa + 2];
+      const double fb0 = sf[qb], fb1 = sf[qb + 1], fb2 = sf[qb + 2];
+      const double Ra0 = xi0 - sx[qa], Ra1 = xi1 - sx[qa + 1], Ra2 = xi2 - sx[qa + 2];
+      const double Rb0 = xi0 - sx[qb], Rb1 = xi1 - sx[qb + 1], Rb2 = xi2 - sx[qb + 2];
+      const double R2a = Ra0 * Ra0 + Ra1 * Ra1 + Ra2 * Ra2;
+      const double R2b = Rb0 * Rb0 + Rb1 * Rb1 + Rb2 * Rb2;
+      double cIa, cRRa, ya, cIb, cRRb, yb;
+      rpy_far_coeffs(R2a, kc, cIa, cRRa, ya);
+      rpy_far_coeffs(R2b, kc, cIb, cRRb, yb);
+      const bool na = !(R2a >= kc.a2x2), nb = !(R2b >= kc.a2x2);
+      if (na || nb) {  // rare: pairs closer than 2a
+        if (na) rpy_near_coeffs(R2a, ya, kc, cIa, cRRa);
+        if (nb) rpy_near_coeffs(R2b, yb, kc, cIb, cRRb);
       }
-      const double rv = cRR * (R0 * f0 + R1 * f1 + R2c * f2);
-      a0 += cI * f0 + rv * R0;
-      a1 += cI * f1 + rv * R1;
-      a2 += cI * f2 + rv * R2c;
+      if (j0 + jj == ii) {  // D_ii = I
+        cIa = 1.0;
+        cRRa = 0.0;
+      }
+      if (j0 + jb == ii) {
+        cIb = 1.0;
+        cRRb = 0.0;
+      }
+      if (!hb) {  // past the chunk: no second bead
+        cIb = 0.0;
+        cRRb = 0.0;
+      }
+      const double rva = cRRa * (Ra0 * fa0 + Ra1 * fa1 + Ra2 * fa2);
+      const double rvb = cRRb * (Rb0 * fb0 + Rb1 * fb1 + Rb2 * fb2);
+      a0 += cIa * fa0 + rva * Ra0;
+      a1 += cIa * fa1 + rva * Ra1;
+      a2 += cIa * fa2 + rva * Ra2;
+      a0 += cIb * fb0 + rvb * Rb0;
+      a1 += cIb * fb1 + rvb * Rb1;
+      a2 += cIb * fb2 + rvb * Rb2;
     }
   }
   // phases jp = 0..3 of this wave: lanes il, il+16, il+32, il+48
