@@ -159,6 +159,65 @@ def measured_traffic(kernel: str):
     return float(rec["hbm_bytes_per_launch"])
 
 
+def ensemble_leg(B, I, torch, np, precs, args, dev) -> dict:
+    """The uneven ensemble (256 chains, N from 64 to 1024, shear at Wi = 10
+    on each chain's relaxation time) advanced by bd_ensemble_step: ensemble
+    steps per second and chain steps per second, plus the Cholesky-equivalent
+    rate sum_c n_c^3/3 flop per step / step time (a lower bound on what the
+    factorisations alone reach, since the step time includes everything)."""
+    w = I.ENSEMBLE_SHEAR
+    sizes = I.ensemble_sizes(w.chains, seed=w.seed)
+    spec = I.ensemble_chains(w, sizes)
+    pgs = [B.make_params(d["n_beads"], dt=w.dt, kappa=d["kappa"], seed=d["seed"],
+                         chain_id=d["chain_id"], hstar=w.hstar, a=w.a, b=w.b) for d in spec]
+    x0 = torch.tensor(np.concatenate([d["x"] for d in spec]), dtype=torch.float64, device=dev)
+    flops = float(sum(chol_flops(3 * int(v)) for v in sizes))
+    out = {"workload": w.name, "chains": int(w.chains), "n_beads_min": int(sizes.min()),
+           "n_beads_max": int(sizes.max()), "sum_n3_over_3": flops}
+    h = B.Handle(0)
+    warm = 2
+    for name, prec in precs.items():
+        xp = x0.clone()
+        ens = B.Ensemble(h, pgs, xp, prec)
+        for s in range(warm):
+            ens.step(s)
+        infos = ens.info()
+        if any(i["status"] != B.OK for i in infos):
+            raise RuntimeError(f"ensemble {name} warmup failed")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.ensemble_steps):
+            ens.step(warm + s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        infos = ens.info()
+        if any(i["status"] != B.OK for i in infos):
+            raise RuntimeError(f"ensemble {name} timed steps failed")
+        h.profile_begin()
+        ens.step(warm + args.ensemble_steps)
+        prof = h.profile_end()
+        ms = 1e3 * wall / args.ensemble_steps
+        chol = {k: v for k, v in prof.items()
+                if k.startswith(("potrf", "panel_solve", "syrk"))}
+        out[name] = {
+            "ensemble_steps_per_s": args.ensemble_steps / wall,
+            "chain_steps_per_s": w.chains * args.ensemble_steps / wall,
+            "ms_per_step": ms,
+            "cholesky_equiv_tflops": flops / (ms * 1e-3) / 1e12,
+            "kernel_ms_per_step": {k: v[1] for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])},
+            "cholesky_kernels_ms_per_step": sum(v[1] for v in chol.values()),
+            "max_newton_iters": max(i["newton_iters"] for i in infos),
+            "max_rod_err": max(i["max_rod_err"] for i in infos),
+        }
+        log(f"ensemble {name}: {out[name]['ensemble_steps_per_s']:.2f} steps/s "
+            f"({ms:.3f} ms/step, {out[name]['chain_steps_per_s']:.0f} chain-steps/s)")
+        ens.close()
+        del ens, xp
+        torch.cuda.empty_cache()
+    h.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +228,10 @@ def main() -> int:
     ap.add_argument("--cpu-beads", type=int, default=4096,
                     help="chain length of the CPU oracle sample (scaled to N=4096 by n^3)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=20,
+                    help="timed steps of the 256-chain ensemble leg (0: skip it)")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="run only the ensemble leg and print its record")
     ap.add_argument("--only", choices=["all", "mixed", "fp64"], default="all",
                     help="restrict the timed steps to one precision (for profiler runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -201,6 +264,11 @@ def main() -> int:
     precs = {"mixed": B.PREC_MIXED, "fp64": B.PREC_FP64}
     if args.only != "all":
         precs = {args.only: precs[args.only]}
+
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": ensemble_leg(B, I, torch, np, precs, args, dev)}), flush=True)
+        h.close()
+        return 0
 
     # ---------------------------------------------------------- step rate
     result = {}
@@ -381,6 +449,8 @@ def main() -> int:
                "measured_s_per_step": dt_s, "status": io["status"]}
         log(f"cpu oracle: {cpu}")
 
+    ens = ensemble_leg(B, I, torch, np, precs, args, dev) if args.ensemble_steps > 0 else None
+
     mixed = result.get("mixed")
     fp64 = result.get("fp64")
     headrec = result[head]
@@ -407,6 +477,7 @@ def main() -> int:
         "kernel_breakdown": breakdown,
         "other_precision_profile": other,
         "cpu_baseline": cpu,
+        "ensemble": ens,
         "context": extra,
     }
     print(json.dumps(out), flush=True)

@@ -160,6 +160,47 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
 /* Synchronise the handle's stream and return the info of the last call. */
 bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out);
 
+/* ---- Ensembles: many independent chains advanced together.  The paper's
+ * production runs average over many independent chains with no exchange
+ * between them (Section 4, one chain per MPI process; Section 5, 128 and
+ * 1000 chains); here every chain of an ensemble shares each launch of each
+ * kernel (the chain is the third grid dimension), so a step of the whole
+ * ensemble costs one launch sequence.
+ *
+ * p[0..n_chains-1]: per-chain parameters (sizes, flows, seeds may all
+ * differ; 1 <= n_chains <= 65535, every N <= 4097).  Positions are packed:
+ * chain c is the N_c x 3 block starting at row sum_{c' < c} N_c' of d_x.
+ * A step of the ensemble advances every chain exactly as bd_step with the
+ * same parameters and `step` would (the same kernels, arithmetic and
+ * reduction orders), with two-panel Cholesky steps for every chain; for
+ * n <= 4096 that is also bd_step's schedule, so the results are bitwise
+ * those of bd_step. */
+typedef struct bd_ensemble_s* bd_ensemble_t;
+
+/* Bytes of device workspace for the ensemble p[0..n_chains-1] in `prec`. */
+bd_status_t bd_ensemble_workspace_size(int32_t n_chains, const bd_params_t* p,
+                                       bd_precision_t prec, size_t* bytes);
+
+/* Build an ensemble on handle h (its stream, lookahead stream and events).
+ * p is copied.  d_x (3 sum_c N_c doubles) and d_ws (>= the size above) stay
+ * caller-owned and bound to the ensemble until bd_ensemble_destroy.  The
+ * ensemble allocates a device table of its chains and one status block per
+ * chain (BD_ERR_ALLOC if that fails). */
+bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_t* p,
+                               bd_precision_t prec, double* d_x, void* d_ws, size_t ws_bytes,
+                               bd_ensemble_t* out);
+
+/* One timestep of every chain with noise counter `step`; d_x is advanced in
+ * place.  A chain whose factorisation fails keeps its positions; its status
+ * and those of the others are reported by bd_ensemble_get_info.  The call
+ * synchronises the stream a few times during the tension solves. */
+bd_status_t bd_ensemble_step(bd_ensemble_t e, int64_t step);
+
+/* Synchronise and write the info of the last step of every chain to
+ * out[0..n_chains-1], in the order of p. */
+bd_status_t bd_ensemble_get_info(bd_ensemble_t e, bd_info_t* out);
+bd_status_t bd_ensemble_destroy(bd_ensemble_t e);
+
 /* Per-kernel timing (instrumentation, not part of the method).  Between
  * bd_profile_begin and bd_profile_end every kernel the handle launches is
  * bracketed by HIP events on the handle's stream.  bd_profile_end

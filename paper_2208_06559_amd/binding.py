@@ -31,7 +31,9 @@ STATUS_NAMES = {0: "BD_OK", 1: "BD_ERR_PARAM", 2: "BD_ERR_NOT_SPD", 3: "BD_ERR_N
 
 EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_rpy_assemble",
            "bd_cholesky", "bd_brownian", "bd_constrain", "bd_step", "bd_get_info",
-           "bd_profile_begin", "bd_profile_end")
+           "bd_profile_begin", "bd_profile_end", "bd_ensemble_workspace_size",
+           "bd_ensemble_create", "bd_ensemble_step", "bd_ensemble_get_info",
+           "bd_ensemble_destroy")
 
 
 class BdError(RuntimeError):
@@ -119,6 +121,12 @@ def lib():
         L.bd_get_info.argtypes = [vp, C.POINTER(Info)]
         L.bd_profile_begin.argtypes = [vp]
         L.bd_profile_end.argtypes = [vp, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]
+        L.bd_ensemble_workspace_size.argtypes = [C.c_int32, pp, C.c_int, C.POINTER(C.c_size_t)]
+        L.bd_ensemble_create.argtypes = [vp, C.c_int32, pp, C.c_int, dp, vp, C.c_size_t,
+                                         C.POINTER(vp)]
+        L.bd_ensemble_step.argtypes = [vp, C.c_int64]
+        L.bd_ensemble_get_info.argtypes = [vp, C.POINTER(Info)]
+        L.bd_ensemble_destroy.argtypes = [vp]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -249,3 +257,54 @@ class Handle:
         out = Info()
         _check(lib().bd_get_info(self._h, C.byref(out)), "bd_get_info")
         return out.as_dict()
+
+
+def ensemble_workspace_size(params, prec: int = PREC_FP64) -> int:
+    arr = (Params * len(params))(*params)
+    out = C.c_size_t(0)
+    _check(lib().bd_ensemble_workspace_size(len(params), arr, prec, C.byref(out)),
+           "bd_ensemble_workspace_size")
+    return int(out.value)
+
+
+class Ensemble:
+    """One bd_ensemble_t: chains with parameters `params` (a list of Params)
+    whose positions are packed in the float64 tensor `x` (chain c's N_c x 3
+    block after those of chains 0..c-1), advanced together by step()."""
+
+    def __init__(self, handle: Handle, params, x: torch.Tensor, prec: int = PREC_FP64):
+        self.handle = handle
+        self.params = list(params)
+        self.count = len(self.params)
+        self.prec = prec
+        n_tot = 3 * sum(p.n_beads for p in self.params)
+        self._arr = (Params * self.count)(*self.params)
+        nbytes = ensemble_workspace_size(self.params, prec)
+        self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=f"cuda:{handle.device}")
+        self.x = x
+        e = C.c_void_p()
+        handle._sync_stream()
+        _check(lib().bd_ensemble_create(handle._h, self.count, self._arr, prec,
+                                        _dev_f64(x, "x", n_tot), self.ws.data_ptr(), nbytes,
+                                        C.byref(e)), "bd_ensemble_create")
+        self._e = e
+
+    def step(self, step: int):
+        self.handle._sync_stream()
+        _check(lib().bd_ensemble_step(self._e, step), "bd_ensemble_step")
+
+    def info(self) -> list[dict]:
+        out = (Info * self.count)()
+        _check(lib().bd_ensemble_get_info(self._e, out), "bd_ensemble_get_info")
+        return [out[c].as_dict() for c in range(self.count)]
+
+    def close(self):
+        if self._e:
+            lib().bd_ensemble_destroy(self._e)
+            self._e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

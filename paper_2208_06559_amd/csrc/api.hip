@@ -5,7 +5,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 #include "profile.hpp"
@@ -61,13 +63,16 @@ struct StepLayout {
   size_t d, chol, brown, cons, y, xs, total;
 };
 
-StepLayout step_layout(int64_t n, bd_precision_t prec) {
+// batched: the layout of one chain of an ensemble (two-panel Cholesky steps)
+StepLayout step_layout(int64_t n, bd_precision_t prec, bool batched = false) {
   StepLayout L;
   size_t off = 0;
   L.d = off;
   off += bd::align_up(sizeof(double) * (size_t)step_ld(n) * (size_t)n, 256);
   L.chol = off;
-  off += bd::align_up(bd::cholesky_workspace_bytes(n, prec), 256);
+  off += bd::align_up(batched ? bd::cholesky_batched_workspace_bytes(n, prec)
+                              : bd::cholesky_workspace_bytes(n, prec),
+                      256);
   L.brown = off;
   off += bd::align_up(bd::brownian_workspace_bytes(n), 256);
   L.cons = off;
@@ -98,6 +103,28 @@ __global__ void commit_positions_kernel(double* x, const double* xs, int64_t n,
   if (e < n) x[e] = xs[e];
 }
 
+// Ensembles: every chain's state (count of them, thread c), and the commit
+// of chain blockIdx.z of the table.
+__global__ void reset_states_kernel(DevState* st, int count) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < count) {
+    st[c].status = BD_OK;
+    st[c].newton_iters = 0;
+    st[c].potrf_info = 0;
+    st[c].max_rod_err = 0.0;
+    st[c].last_newton_res = 0.0;
+    st[c].krylov_iters = 0;
+    st[c].done = 0;
+  }
+}
+
+__global__ void commit_positions_batched_kernel(const bd::ChainDesc* cd) {
+  const bd::ChainDesc& c = cd[blockIdx.z];
+  if (c.st->status == BD_ERR_NOT_SPD) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < c.n) c.x[e] = c.xs[e];
+}
+
 bd_status_t hip_status(hipError_t e) { return e == hipSuccess ? BD_OK : BD_ERR_HIP; }
 
 // Makes the handle's device current and its profiler (if on) active for the
@@ -118,6 +145,19 @@ hipError_t reset(bd_handle_t h) {
 }
 
 }  // namespace
+
+struct bd_ensemble_s {
+  bd_handle_t h;
+  int count;
+  bd_precision_t prec;
+  int max_beads;
+  int newton_maxit;                  // largest over the chains
+  bd::ChainDesc* cd;                 // device table, decreasing n
+  std::vector<bd::ChainDesc> host;   // its host copy
+  DevState* st;                      // device, one per chain in the caller's order
+  DevState* host_st;                 // pinned mirror
+  int pairs_hint;
+};
 
 extern "C" {
 
@@ -337,6 +377,180 @@ bd_status_t bd_profile_end(bd_handle_t h, bd_kernel_stat_t* out, int32_t max_out
   const int n = bd::profiler_collect(h->prof, h->stream, out, max_out);
   if (n_out) *n_out = n;
   h->prof_on = 0;
+  return BD_OK;
+}
+
+// ---------------------------------------------------------------- ensembles
+
+static bool ensemble_args_ok(int32_t n_chains, const bd_params_t* p) {
+  if (n_chains < 1 || n_chains > 65535 || !p) return false;
+  for (int32_t c = 0; c < n_chains; ++c)
+    if (!params_ok(&p[c])) return false;
+  return true;
+}
+
+static bool ensemble_sizes_ok(int32_t n_chains, const bd_params_t* p) {
+  for (int32_t c = 0; c < n_chains; ++c)
+    if (p[c].n_beads > bd::constrain_max_beads()) return false;
+  return true;
+}
+
+bd_status_t bd_ensemble_workspace_size(int32_t n_chains, const bd_params_t* p,
+                                       bd_precision_t prec, size_t* bytes) {
+  if (!bytes || !prec_ok(prec) || !ensemble_args_ok(n_chains, p)) return BD_ERR_PARAM;
+  if (!ensemble_sizes_ok(n_chains, p)) return BD_ERR_UNSUPPORTED;
+  size_t total = 0;
+  for (int32_t c = 0; c < n_chains; ++c) total += step_layout(3 * (int64_t)p[c].n_beads, prec, true).total;
+  *bytes = total;
+  return BD_OK;
+}
+
+static void ensemble_release(bd_ensemble_s* e) {
+  if (e->cd) (void)hipFree(e->cd);
+  if (e->st) (void)hipFree(e->st);
+  if (e->host_st) (void)hipHostFree(e->host_st);
+  delete e;
+}
+
+bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_t* p,
+                               bd_precision_t prec, double* d_x, void* d_ws, size_t ws_bytes,
+                               bd_ensemble_t* out) {
+  if (!out) return BD_ERR_PARAM;
+  *out = nullptr;
+  bd_status_t err = enter(h);
+  if (err != BD_OK) return err;
+  if (!d_x || !d_ws || !prec_ok(prec) || !ensemble_args_ok(n_chains, p)) return BD_ERR_PARAM;
+  if (!ensemble_sizes_ok(n_chains, p)) return BD_ERR_UNSUPPORTED;
+  size_t need = 0;
+  if (bd_ensemble_workspace_size(n_chains, p, prec, &need) != BD_OK || ws_bytes < need)
+    return BD_ERR_PARAM;
+  bd_ensemble_s* e = new (std::nothrow) bd_ensemble_s;
+  if (!e) return BD_ERR_ALLOC;
+  e->h = h;
+  e->count = n_chains;
+  e->prec = prec;
+  e->max_beads = 0;
+  e->newton_maxit = 1;
+  e->cd = nullptr;
+  e->st = nullptr;
+  e->host_st = nullptr;
+  e->pairs_hint = 0;
+  if (hipMalloc(&e->cd, sizeof(bd::ChainDesc) * (size_t)n_chains) != hipSuccess ||
+      hipMalloc(&e->st, sizeof(DevState) * (size_t)n_chains) != hipSuccess ||
+      hipHostMalloc(&e->host_st, sizeof(DevState) * (size_t)n_chains, hipHostMallocDefault) !=
+          hipSuccess) {
+    ensemble_release(e);
+    return BD_ERR_ALLOC;
+  }
+  try {
+    e->host.resize((size_t)n_chains);
+  } catch (...) {
+    ensemble_release(e);
+    return BD_ERR_ALLOC;
+  }
+  char* base = static_cast<char*>(d_ws);
+  int64_t xoff = 0;
+  for (int32_t c = 0; c < n_chains; ++c) {
+    const bd_params_t& q = p[c];
+    const int64_t n = 3 * (int64_t)q.n_beads;
+    const StepLayout L = step_layout(n, prec, true);
+    bd::ChainDesc& d = e->host[(size_t)c];
+    memset(&d, 0, sizeof(d));
+    d.N = q.n_beads;
+    d.uniform = (q.noise == BD_NOISE_UNIFORM_PAPER) ? 1 : 0;
+    d.n = n;
+    d.ld = step_ld(n);
+    d.hstar = q.hstar;
+    d.a = q.a;
+    d.b = q.b;
+    d.dt = q.dt;
+    d.tol = q.newton_tol;
+    d.cB = d.uniform ? sqrt(6.0 * q.dt) : sqrt(2.0 * q.dt);
+    d.maxit = q.newton_maxit;
+    d.index = c;
+    for (int k = 0; k < 9; ++k) d.kappa[k] = q.kappa[k];
+    d.seed = q.seed;
+    d.chain_id = q.chain_id;
+    d.x = d_x + xoff;
+    d.D = reinterpret_cast<double*>(base + L.d);
+    d.W = reinterpret_cast<double*>(base + L.chol);
+    if (prec == BD_PREC_MIXED) {
+      char* pc = base + L.chol + bd::align_up(sizeof(double) * bd::kNB * bd::kNB, 256);
+      d.P32[0] = reinterpret_cast<float*>(pc);
+      d.P32[1] = reinterpret_cast<float*>(pc + bd::align_up(sizeof(float) * (size_t)n * 2 * bd::kNB, 256));
+    }
+    d.xi = reinterpret_cast<double*>(base + L.brown);
+    d.part = reinterpret_cast<double*>(base + L.brown + bd::align_up(sizeof(double) * n, 256));
+    d.y = reinterpret_cast<double*>(base + L.y);
+    d.xs = reinterpret_cast<double*>(base + L.xs);
+    d.cons = base + L.cons;
+    d.st = e->st + c;
+    base += L.total;
+    xoff += n;
+    if (q.n_beads > e->max_beads) e->max_beads = q.n_beads;
+    if (q.newton_maxit > e->newton_maxit) e->newton_maxit = q.newton_maxit;
+  }
+  // decreasing n (ties in the caller's order): the chains with work at a
+  // given column of the factorisation are a prefix of the table
+  std::stable_sort(e->host.begin(), e->host.end(),
+                   [](const bd::ChainDesc& a, const bd::ChainDesc& b) { return a.n > b.n; });
+  memset(e->host_st, 0, sizeof(DevState) * (size_t)n_chains);
+  if (hipMemcpy(e->cd, e->host.data(), sizeof(bd::ChainDesc) * (size_t)n_chains,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(e->st, e->host_st, sizeof(DevState) * (size_t)n_chains, hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    ensemble_release(e);
+    return BD_ERR_HIP;
+  }
+  *out = e;
+  return BD_OK;
+}
+
+bd_status_t bd_ensemble_step(bd_ensemble_t e, int64_t step) {
+  if (!e) return BD_ERR_PARAM;
+  bd_handle_t h = e->h;
+  CallScope scope(h);
+  bd_status_t err = enter(h);
+  if (err != BD_OK) return err;
+  hipStream_t s = h->stream;
+  const int z = e->count;
+  const int64_t max_n = 3 * (int64_t)e->max_beads;
+  BD_LAUNCH("reset_states", reset_states_kernel, dim3((unsigned)((z + 255) / 256)), dim3(256), 0,
+            s, e->st, z);
+  hipError_t he = hipGetLastError();
+  if (he == hipSuccess) he = bd::launch_rpy_assemble_batched(s, e->cd, z, e->max_beads);
+  if (he == hipSuccess)
+    he = bd::launch_cholesky_batched(s, h->aux, h->ev, e->cd, e->host.data(), z, e->prec);
+  if (he == hipSuccess) he = bd::launch_brownian_batched(s, e->cd, z, max_n, step);
+  if (he == hipSuccess) he = bd::launch_predictor_batched(s, e->cd, z, e->max_beads);
+  if (he == hipSuccess)
+    he = bd::launch_constrain_batched(s, e->cd, z, e->max_beads, e->newton_maxit, e->st,
+                                      e->host_st, &e->pairs_hint);
+  if (he == hipSuccess) {
+    BD_LAUNCH("commit_positions_batched", commit_positions_batched_kernel,
+              dim3((unsigned)((max_n + 255) / 256), 1, z), dim3(256), 0, s, e->cd);
+    he = hipGetLastError();
+  }
+  return hip_status(he);
+}
+
+bd_status_t bd_ensemble_get_info(bd_ensemble_t e, bd_info_t* out) {
+  if (!e || !out) return BD_ERR_PARAM;
+  bd_status_t err = enter(e->h);
+  if (err != BD_OK) return err;
+  if (hipMemcpyAsync(e->host_st, e->st, sizeof(DevState) * (size_t)e->count,
+                     hipMemcpyDeviceToHost, e->h->stream) != hipSuccess)
+    return BD_ERR_HIP;
+  if (hipStreamSynchronize(e->h->stream) != hipSuccess) return BD_ERR_HIP;
+  for (int c = 0; c < e->count; ++c) memcpy(&out[c], &e->host_st[c], sizeof(bd_info_t));
+  return BD_OK;
+}
+
+bd_status_t bd_ensemble_destroy(bd_ensemble_t e) {
+  if (!e) return BD_ERR_PARAM;
+  (void)hipSetDevice(e->h->device);
+  (void)hipStreamSynchronize(e->h->stream);
+  ensemble_release(e);
   return BD_OK;
 }
 

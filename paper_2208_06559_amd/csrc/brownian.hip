@@ -26,10 +26,10 @@ __device__ __forceinline__ void tri_index(int t, int& r, int& c) {
   c = t - rr * (rr + 1) / 2;
 }
 
-__global__ __launch_bounds__(256) void noise_kernel(double* __restrict__ xi, int64_t n,
-                                                     uint64_t seed, uint64_t chain,
-                                                     uint64_t step, int uniform) {
-  const int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void noise_body(int bx, double* __restrict__ xi, int64_t n,
+                                           uint64_t seed, uint64_t chain, uint64_t step,
+                                           int uniform) {
+  const int64_t blk = (int64_t)bx * blockDim.x + threadIdx.x;
   if (blk * 4 >= n) return;
   double z[4];
   noise4(seed, chain, step, (uint64_t)blk, uniform, z);
@@ -38,12 +38,18 @@ __global__ __launch_bounds__(256) void noise_kernel(double* __restrict__ xi, int
     if (blk * 4 + l < n) xi[blk * 4 + l] = z[l];
 }
 
-__global__ __launch_bounds__(kTv) void trmv_tile_kernel(const double* __restrict__ L, int64_t ld,
-                                                         int64_t n, const double* __restrict__ xi,
-                                                         double* __restrict__ part) {
+__global__ __launch_bounds__(256) void noise_kernel(double* __restrict__ xi, int64_t n,
+                                                     uint64_t seed, uint64_t chain,
+                                                     uint64_t step, int uniform) {
+  noise_body(blockIdx.x, xi, n, seed, chain, step, uniform);
+}
+
+__device__ __forceinline__ void trmv_tile_body(int t, const double* __restrict__ L, int64_t ld,
+                                               int64_t n, const double* __restrict__ xi,
+                                               double* __restrict__ part) {
   __shared__ double xs[kTv];
   int rt, ct;
-  tri_index(blockIdx.x, rt, ct);
+  tri_index(t, rt, ct);
   const int64_t i = (int64_t)rt * kTv + threadIdx.x;
   const int64_t j0 = (int64_t)ct * kTv;
   {
@@ -68,10 +74,15 @@ __global__ __launch_bounds__(kTv) void trmv_tile_kernel(const double* __restrict
   part[(int64_t)ct * n + i] = (acc0 + acc1) + (acc2 + acc3);
 }
 
-__global__ __launch_bounds__(256) void trmv_reduce_kernel(const double* __restrict__ part,
-                                                           int64_t n, double c,
-                                                           double* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kTv) void trmv_tile_kernel(const double* __restrict__ L, int64_t ld,
+                                                         int64_t n, const double* __restrict__ xi,
+                                                         double* __restrict__ part) {
+  trmv_tile_body(blockIdx.x, L, ld, n, xi, part);
+}
+
+__device__ __forceinline__ void trmv_reduce_body(int bx, const double* __restrict__ part,
+                                                 int64_t n, double c, double* __restrict__ y) {
+  const int64_t i = (int64_t)bx * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int rt = (int)(i / kTv);
   double s = 0.0;
@@ -79,13 +90,19 @@ __global__ __launch_bounds__(256) void trmv_reduce_kernel(const double* __restri
   y[i] = c * s;
 }
 
-__global__ __launch_bounds__(256) void predictor_kernel(const double* __restrict__ x,
-                                                         const double* __restrict__ y,
-                                                         double* __restrict__ xs, int N, double dt,
-                                                         double k0, double k1, double k2,
-                                                         double k3, double k4, double k5,
-                                                         double k6, double k7, double k8) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void trmv_reduce_kernel(const double* __restrict__ part,
+                                                           int64_t n, double c,
+                                                           double* __restrict__ y) {
+  trmv_reduce_body(blockIdx.x, part, n, c, y);
+}
+
+__device__ __forceinline__ void predictor_body(int bx, const double* __restrict__ x,
+                                               const double* __restrict__ y,
+                                               double* __restrict__ xs, int N, double dt,
+                                               double k0, double k1, double k2, double k3,
+                                               double k4, double k5, double k6, double k7,
+                                               double k8) {
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const double r0 = x[3 * i], r1 = x[3 * i + 1], r2 = x[3 * i + 2];
   // Eq. 5 flow term kappa . r_i, unweighted by D (Eq. 6)
@@ -95,6 +112,41 @@ __global__ __launch_bounds__(256) void predictor_kernel(const double* __restrict
   xs[3 * i] = r0 + dt * v0 + y[3 * i];
   xs[3 * i + 1] = r1 + dt * v1 + y[3 * i + 1];
   xs[3 * i + 2] = r2 + dt * v2 + y[3 * i + 2];
+}
+
+__global__ __launch_bounds__(256) void predictor_kernel(const double* __restrict__ x,
+                                                         const double* __restrict__ y,
+                                                         double* __restrict__ xs, int N, double dt,
+                                                         double k0, double k1, double k2,
+                                                         double k3, double k4, double k5,
+                                                         double k6, double k7, double k8) {
+  predictor_body(blockIdx.x, x, y, xs, N, dt, k0, k1, k2, k3, k4, k5, k6, k7, k8);
+}
+
+// Ensembles: chain blockIdx.z of the table; grids cover the largest chain.
+__global__ __launch_bounds__(256) void noise_batched_kernel(const ChainDesc* __restrict__ cd,
+                                                             uint64_t step) {
+  const ChainDesc& c = cd[blockIdx.z];
+  noise_body(blockIdx.x, c.xi, c.n, c.seed, c.chain_id, step, c.uniform);
+}
+
+__global__ __launch_bounds__(kTv) void trmv_tile_batched_kernel(const ChainDesc* __restrict__ cd) {
+  const ChainDesc& c = cd[blockIdx.z];
+  const int64_t nt = (c.n + kTv - 1) / kTv;
+  if ((int64_t)blockIdx.x >= nt * (nt + 1) / 2) return;
+  trmv_tile_body(blockIdx.x, c.D, c.ld, c.n, c.xi, c.part);
+}
+
+__global__ __launch_bounds__(256) void trmv_reduce_batched_kernel(const ChainDesc* __restrict__ cd) {
+  const ChainDesc& c = cd[blockIdx.z];
+  trmv_reduce_body(blockIdx.x, c.part, c.n, c.cB, c.y);
+}
+
+__global__ __launch_bounds__(256) void predictor_batched_kernel(const ChainDesc* __restrict__ cd) {
+  const ChainDesc& c = cd[blockIdx.z];
+  const double* k = c.kappa;
+  predictor_body(blockIdx.x, c.x, c.y, c.xs, c.N, c.dt, k[0], k[1], k[2], k[3], k[4], k[5], k[6],
+                 k[7], k[8]);
 }
 
 }  // namespace
@@ -134,6 +186,25 @@ hipError_t launch_predictor(hipStream_t s, const bd_params_t& p, const double* x
   const double* k = p.kappa;
   BD_LAUNCH("predictor", predictor_kernel, dim3((N + 255) / 256), dim3(256), 0, s, x, y, xs, N, p.dt,
                      k[0], k[1], k[2], k[3], k[4], k[5], k[6], k[7], k[8]);
+  return hipGetLastError();
+}
+
+hipError_t launch_brownian_batched(hipStream_t s, const ChainDesc* cd, int count, int64_t max_n,
+                                   int64_t step) {
+  const int64_t nblk = (max_n + 3) / 4;
+  BD_LAUNCH("noise_batched", noise_batched_kernel,
+            dim3((unsigned)((nblk + 255) / 256), 1, count), dim3(256), 0, s, cd, (uint64_t)step);
+  const int64_t nt = trmv_tiles(max_n);
+  BD_LAUNCH("trmv_tile_batched", trmv_tile_batched_kernel,
+            dim3((unsigned)(nt * (nt + 1) / 2), 1, count), dim3(kTv), 0, s, cd);
+  BD_LAUNCH("trmv_reduce_batched", trmv_reduce_batched_kernel,
+            dim3((unsigned)((max_n + 255) / 256), 1, count), dim3(256), 0, s, cd);
+  return hipGetLastError();
+}
+
+hipError_t launch_predictor_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads) {
+  BD_LAUNCH("predictor_batched", predictor_batched_kernel,
+            dim3((max_beads + 255) / 256, 1, count), dim3(256), 0, s, cd);
   return hipGetLastError();
 }
 

@@ -802,10 +802,9 @@ __device__ __forceinline__ void invert_diag_tiles(const d4& D0, const d4& D1, do
   }
 }
 
-__global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A, int64_t ld,
-                                                          int64_t k, int nb,
-                                                          double* __restrict__ W,
-                                                          DevState* __restrict__ st) {
+__device__ __forceinline__ void potrf_tile_body(double* __restrict__ A, int64_t ld, int64_t k,
+                                                int nb, double* __restrict__ W,
+                                                DevState* __restrict__ st) {
   // published column blocks (double buffer); after the last of them has
   // been applied, the diagonal 32 x 32 blocks of L (column-major) for the
   // inversion
@@ -840,6 +839,13 @@ __global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A,
     st->status = BD_ERR_NOT_SPD;
   }
   invert_diag_tiles(T0[0], T1[0], Ld, rdg, W, w, lr, lk);
+}
+
+__global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A, int64_t ld,
+                                                          int64_t k, int nb,
+                                                          double* __restrict__ W,
+                                                          DevState* __restrict__ st) {
+  potrf_tile_body(A, ld, k, nb, W, st);
 }
 
 // ------------------------------------------------------------------------
@@ -892,14 +898,15 @@ __device__ __forceinline__ void solve_subpanel(double (&x)[NB / 4], const double
     for (int q = 0; q < 4; ++q) x[c0 / 4 + 4 * jt + q] = y[jt][q];
 }
 
-__global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
-    double* __restrict__ A, int64_t ld, int64_t k, int nb, int64_t m, const double* __restrict__ W,
-    float* __restrict__ P32, int64_t ldp) {
+__device__ __forceinline__ void panel_solve_body(int bx, double* __restrict__ A, int64_t ld,
+                                                 int64_t k, int nb, int64_t m,
+                                                 const double* __restrict__ W,
+                                                 float* __restrict__ P32, int64_t ldp) {
   static_assert(NSB == 4 && res_row_f64_is_lk_plus_4r, "register layout of the panel solve");
   __builtin_amdgcn_s_setprio(3);  // critical path, like the diagonal block
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-  const int64_t row = (int64_t)blockIdx.x * kRB + 16 * w + lr;
+  const int64_t row = (int64_t)bx * kRB + 16 * w + lr;
   const bool live = row < m;
   double* A21 = A + k * ld + k + nb;
   const double* L11 = A + k * ld + k;
@@ -922,6 +929,12 @@ __global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
       if (P32) P32[(int64_t)c * ldp + row] = (float)x[t];
     }
   }
+}
+
+__global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
+    double* __restrict__ A, int64_t ld, int64_t k, int nb, int64_t m, const double* __restrict__ W,
+    float* __restrict__ P32, int64_t ldp) {
+  panel_solve_body(blockIdx.x, A, ld, k, nb, m, W, P32, ldp);
 }
 
 // ------------------------------------------------------------------------
@@ -963,10 +976,9 @@ enum { kTilesAll = 0, kTilesNext = 1, kTilesRest = 2 };
 // is read in the epilogue.  Registers and LDS are sized for two workgroups
 // per CU, so one workgroup's loads and stores overlap the other's MFMAs.
 template <typename T, int TS>
-__global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict__ C, int64_t ld,
-                                                              const T* __restrict__ L, int64_t ldl,
-                                                              int64_t m, int kdim, int tiles,
-                                                              int nnext) {
+__device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, int64_t ld,
+                                                 const T* __restrict__ L, int64_t ldl, int64_t m,
+                                                 int kdim, int tiles, int nnext) {
   constexpr int KC = SyrkCfg<T>::KC;
   typedef typename SyrkCfg<T>::acc_t acc_t;
   constexpr int WT = TS / 2;           // each wave owns a WT x WT quadrant
@@ -980,9 +992,6 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
   __shared__ __attribute__((aligned(16))) T As[2][TS][LR];  // row side, [row][k]
   __shared__ __attribute__((aligned(16))) T Bs[2][TS][LR];  // column side
 
-  // XCD x receives workgroups x, x+8, ...: cnt(x) = base + (x < rem) of them;
-  // the q-th of them takes tile x*base + min(x, rem) + q (a bijection).
-  const int t = xcd_contiguous(blockIdx.x, gridDim.x);
   int ti, tj;
   if (tiles == kTilesNext) {
     // tile column q holds tiles q .. mt-1; columns 0 .. nnext-1 in order
@@ -1109,7 +1118,82 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
   }
 }
 
+// XCD x receives workgroups x, x+8, ...: cnt(x) = base + (x < rem) of them;
+// the q-th of them takes tile x*base + min(x, rem) + q (a bijection).
+template <typename T, int TS>
+__global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict__ C, int64_t ld,
+                                                              const T* __restrict__ L, int64_t ldl,
+                                                              int64_t m, int kdim, int tiles,
+                                                              int nnext) {
+  syrk_update_body<T, TS>(xcd_contiguous(blockIdx.x, gridDim.x), C, ld, L, ldl, m, kdim, tiles,
+                          nnext);
+}
+
+// ------------------------------------------------------------------------
+// 4. Ensembles: the same kernels over a table of chains, chain blockIdx.z.
+//    The host schedule is common to every chain (two-panel steps from
+//    column 0); each workgroup derives its chain's panel width, row count
+//    and tile set from the chain's n and returns at once where the chain
+//    has no work.  Grids cover the largest chain still active.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void potrf_tile_batched_kernel(const ChainDesc* __restrict__ cd,
+                                                                  int64_t k) {
+  const ChainDesc& c = cd[blockIdx.z];
+  if (k >= c.n) return;
+  potrf_tile_body(c.D, c.ld, k, (c.n - k < NB) ? (int)(c.n - k) : NB, c.W, c.st);
+}
+
+// Panel kp of the step starting at k0, whose FP32 copy (MIXED) is P32[pidx].
+__global__ __launch_bounds__(kPsThreads) void panel_solve_batched_kernel(
+    const ChainDesc* __restrict__ cd, int64_t k0, int64_t kp, int pidx) {
+  const ChainDesc& c = cd[blockIdx.z];
+  const int64_t m = c.n - kp - NB;
+  if (m <= 0 || (int64_t)blockIdx.x * kRB >= m) return;
+  float* P = c.P32[pidx];
+  if (P) P += (kp - k0) * c.n + kp + NB;
+  panel_solve_body(blockIdx.x, c.D, c.ld, kp, NB, m, c.W, P, c.n);
+}
+
+// Tile set `tiles` of the update of the trailing matrix from row r0 by the
+// kdim columns from k0; nnext_panels caps the panels of the chain's next
+// step (the tile columns updated ahead).
+template <typename T, int TS>
+__global__ __launch_bounds__(256, 2) void syrk_update_batched_kernel(
+    const ChainDesc* __restrict__ cd, int64_t k0, int64_t r0, int kdim, int tiles,
+    int nnext_panels, int pidx) {
+  const ChainDesc& c = cd[blockIdx.z];
+  const int64_t m = c.n - r0;
+  if (m <= 0) return;
+  const int64_t mt = (m + TS - 1) / TS;
+  int64_t np = (m + NB - 1) / NB;
+  if (np > nnext_panels) np = nnext_panels;
+  int64_t nnext = np * (NB / TS);
+  if (nnext > mt) nnext = mt;
+  int64_t nt = 0;
+  if (tiles == kTilesAll) nt = mt * (mt + 1) / 2;
+  if (tiles == kTilesNext) nt = nnext * mt - nnext * (nnext - 1) / 2;
+  if (tiles == kTilesRest) nt = (mt - nnext) * (mt - nnext + 1) / 2;
+  const int t = xcd_contiguous(blockIdx.x, gridDim.x);
+  if (t >= nt) return;
+  const T* L;
+  int64_t ldl;
+  if constexpr (sizeof(T) == 4) {
+    L = c.P32[pidx] + r0;
+    ldl = c.n;
+  } else {
+    L = c.D + k0 * c.ld + r0;
+    ldl = c.ld;
+  }
+  syrk_update_body<T, TS>(t, c.D + r0 * c.ld + r0, c.ld, L, ldl, m, kdim, tiles, (int)nnext);
+}
+
 }  // namespace
+
+size_t cholesky_batched_workspace_bytes(int64_t n, bd_precision_t prec) {
+  size_t b = align_up(sizeof(double) * NB * NB, 256);
+  if (prec == BD_PREC_MIXED) b += 2 * align_up(sizeof(float) * (size_t)n * 2 * NB, 256);
+  return b;
+}
 
 size_t cholesky_workspace_bytes(int64_t n, bd_precision_t prec) {
   size_t b = align_up(sizeof(double) * NB * NB, 256);  // four 32 x 32 inverses (NB*NB/4 used)
@@ -1286,6 +1370,124 @@ hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int
     if ((e = hipEventRecord(ev_rest, s)) != hipSuccess) return e;
     k = r0;
     w = wn;
+  }
+  if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+namespace {
+
+// The batched schedule: the chains of the table in decreasing order of n,
+// so that the chains with work at column k are a prefix of it.
+struct BatchCtx {
+  const ChainDesc* cd;       // device table
+  const ChainDesc* host;     // its host copy
+  int count;
+  bool mixed;
+};
+
+constexpr int64_t kBatchStep = 2 * NB;  // two panels per step for every chain
+
+// Chains with n > k.
+int active(const BatchCtx& b, int64_t k) {
+  int a = 0;
+  while (a < b.count && b.host[a].n > k) ++a;
+  return a;
+}
+
+int batch_pidx(int64_t k0) { return (int)((k0 / kBatchStep) & 1); }
+
+hipError_t batch_trailing(const BatchCtx& b, hipStream_t s, int64_t k0, int64_t r0, int kdim,
+                          int tiles, int nnext_panels) {
+  const int z = active(b, r0);
+  if (z == 0) return hipSuccess;
+  const int ts = (tiles == kTilesNext) ? kTS / 2 : kTS;
+  // grid for the largest chain (the first of the table)
+  const int64_t m = b.host[0].n - r0;
+  const int64_t mt = (m + ts - 1) / ts;
+  int64_t np = (m + NB - 1) / NB;
+  if (np > nnext_panels) np = nnext_panels;
+  int64_t nnext = np * (NB / ts);
+  if (nnext > mt) nnext = mt;
+  int64_t nt = 0;
+  if (tiles == kTilesAll) nt = mt * (mt + 1) / 2;
+  if (tiles == kTilesNext) nt = nnext * mt - nnext * (nnext - 1) / 2;
+  if (tiles == kTilesRest) nt = (mt - nnext) * (mt - nnext + 1) / 2;
+  if (nt <= 0) return hipSuccess;
+  const dim3 grid((unsigned)nt, 1, z);
+  const int pidx = batch_pidx(k0);
+  if (b.mixed && ts == kTS)
+    BD_LAUNCH("syrk_update_f32_batched", (syrk_update_batched_kernel<float, kTS>), grid, dim3(256),
+              0, s, b.cd, k0, r0, kdim, tiles, nnext_panels, pidx);
+  else if (b.mixed)
+    BD_LAUNCH("syrk_next_f32_batched", (syrk_update_batched_kernel<float, kTS / 2>), grid,
+              dim3(256), 0, s, b.cd, k0, r0, kdim, tiles, nnext_panels, pidx);
+  else if (ts == kTS)
+    BD_LAUNCH("syrk_update_f64_batched", (syrk_update_batched_kernel<double, kTS>), grid,
+              dim3(256), 0, s, b.cd, k0, r0, kdim, tiles, nnext_panels, pidx);
+  else
+    BD_LAUNCH("syrk_next_f64_batched", (syrk_update_batched_kernel<double, kTS / 2>), grid,
+              dim3(256), 0, s, b.cd, k0, r0, kdim, tiles, nnext_panels, pidx);
+  return hipGetLastError();
+}
+
+hipError_t batch_factor_step(const BatchCtx& b, hipStream_t s, int64_t k0) {
+  hipError_t e;
+  for (int64_t kp = k0; kp < k0 + kBatchStep; kp += NB) {
+    const int z = active(b, kp);
+    if (z == 0) break;
+    if (kp > k0 && (e = batch_trailing(b, s, k0, kp, (int)(kp - k0), kTilesNext, 1)) != hipSuccess)
+      return e;
+    BD_LAUNCH("potrf_tile_batched", potrf_tile_batched_kernel, dim3(1, 1, z), dim3(256), 0, s,
+              b.cd, kp);
+    const int zp = active(b, kp + NB);  // chains whose panel has rows below it
+    if (zp > 0) {
+      const int64_t m = b.host[0].n - kp - NB;
+      BD_LAUNCH("panel_solve_batched", panel_solve_batched_kernel,
+                dim3((unsigned)((m + kRB - 1) / kRB), 1, zp), dim3(kPsThreads), 0, s, b.cd, k0,
+                kp, batch_pidx(k0));
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+// launch_cholesky's lookahead schedule, two panels per step, over every
+// chain of the table at once.
+hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev[4],
+                                   const ChainDesc* cd, const ChainDesc* cd_host, int count,
+                                   bd_precision_t prec) {
+  if (count <= 0) return hipSuccess;
+  BatchCtx b{cd, cd_host, count, prec == BD_PREC_MIXED};
+  const int64_t n = cd_host[0].n;  // the largest chain
+  const int64_t w = kBatchStep;
+  hipError_t e;
+  if (!aux) {
+    for (int64_t k = 0; k < n; k += w) {
+      if ((e = batch_factor_step(b, s, k)) != hipSuccess) return e;
+      if (k + w < n && (e = batch_trailing(b, s, k, k + w, (int)w, kTilesAll, 0)) != hipSuccess)
+        return e;
+    }
+    return hipGetLastError();
+  }
+  hipEvent_t ev_fork = ev[0], ev_panel = ev[1], ev_rest = ev[2], ev_next = ev[3];
+  if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
+  if ((e = batch_factor_step(b, aux, 0)) != hipSuccess) return e;
+  if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
+  for (int64_t k = 0; k + w < n; k += w) {
+    const int64_t r0 = k + w;
+    if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
+    if (k > 0 && (e = hipStreamWaitEvent(aux, ev_rest, 0)) != hipSuccess) return e;
+    if ((e = batch_trailing(b, aux, k, r0, (int)w, kTilesNext, 2)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev_next, aux)) != hipSuccess) return e;
+    if ((e = batch_factor_step(b, aux, r0)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, ev_next, 0)) != hipSuccess) return e;
+    if ((e = batch_trailing(b, s, k, r0, (int)w, kTilesRest, 2)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev_rest, s)) != hipSuccess) return e;
   }
   if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
   return hipGetLastError();

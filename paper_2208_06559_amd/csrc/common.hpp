@@ -56,6 +56,54 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
                             double* T_out, void* ws, DevState* st, DevState* host_state_pinned,
                             int* pairs_hint);
 
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- ensembles
+// One chain of an ensemble as the batched kernels see it: the chain's
+// parameters and the absolute device addresses of its data.  A batched
+// launch takes a table of these and works on chain blockIdx.z of it; each
+// workgroup derives its chain's sizes from the entry and returns at once if
+// the chain has no work at its grid position.
+struct ChainDesc {
+  int32_t N;          // beads
+  int32_t uniform;    // 1: the paper's uniform noise (Eq. 2), 0: Gaussian
+  int64_t n;          // 3N
+  int64_t ld;         // leading dimension of D
+  double hstar, a, b, dt, tol, cB;  // cB: noise coefficient sqrt(2 dt) or sqrt(6 dt)
+  int32_t maxit;
+  int32_t index;      // position of the chain in the caller's order
+  double kappa[9];
+  uint64_t seed, chain_id;
+  double* x;          // N x 3 positions (in the packed array of the ensemble)
+  double* D;          // n x ld diffusion tensor, then its factor
+  double* W;          // Cholesky: inverses of the diagonal sub-blocks
+  float* P32[2];      // Cholesky MIXED: FP32 panel copies of alternate steps (n x 2 NB)
+  double* xi;         // noise (n)
+  double* part;       // TRMV partial sums
+  double* y;          // Brownian displacement (n)
+  double* xs;         // predictor / new positions (N x 3)
+  void* cons;         // tension-solve workspace
+  DevState* st;       // status of this chain
+};
+
+// Bytes each chain of an ensemble needs in the Cholesky workspace (two-panel
+// steps, so the FP32 panel copies are n x 2 NB).
+size_t cholesky_batched_workspace_bytes(int64_t n, bd_precision_t prec);
+// The chains of `cd` (device table, `cd_host` its host copy) ordered by
+// decreasing n, `count` of them; every chain is factored in place with the
+// schedule of launch_cholesky at two panels per step.
+hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev[4],
+                                   const ChainDesc* cd, const ChainDesc* cd_host, int count,
+                                   bd_precision_t prec);
+hipError_t launch_rpy_assemble_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads);
+hipError_t launch_brownian_batched(hipStream_t s, const ChainDesc* cd, int count, int64_t max_n,
+                                   int64_t step);
+hipError_t launch_predictor_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads);
+// Runs the tension solve of every chain; returns once every chain's
+// iteration has finished (polls the `count` states at `st`, which are
+// contiguous, through the pinned `host_states`).
+hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads,
+                                    int newton_maxit, DevState* st, DevState* host_states,
+                                    int* pairs_hint);
 
 }  // namespace bd

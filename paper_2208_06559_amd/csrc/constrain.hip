@@ -49,7 +49,7 @@ struct Bufs {
 };
 
 
-Bufs carve(void* ws, int N) {
+__host__ __device__ Bufs carve(void* ws, int N) {
   const int64_t M = N - 1;
   char* p = static_cast<char*>(ws);
   auto take = [&](size_t count) {
@@ -95,7 +95,7 @@ struct RpyConst {
   double near_rr;   // 3 h*/(8a) / (4a)
 };
 
-RpyConst rpy_const(double hstar, double a) {
+__host__ __device__ RpyConst rpy_const(double hstar, double a) {
   RpyConst c;
   c.a2x2 = 4.0 * a * a;
   c.far_pre = 0.75 * hstar;
@@ -167,12 +167,11 @@ __device__ __forceinline__ void unit_bond(const double* __restrict__ x, int k, d
   u[0] = q0 / nq; u[1] = q1 / nq; u[2] = q2 / nq;
 }
 
-__global__ __launch_bounds__(256) void constrain_init_kernel(const double* __restrict__ x_old,
-                                                              const double* __restrict__ xs,
-                                                              Bufs b, int N, double hstar,
-                                                              double a, DevState* st) {
+__device__ __forceinline__ void constrain_init_body(int bx, const double* __restrict__ x_old,
+                                                    const double* __restrict__ xs, Bufs b, int N,
+                                                    double hstar, double a, DevState* st) {
   const int M = N - 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = bx * blockDim.x + threadIdx.x;
   if (t < M) {
     const int k = t;
     double u[3];
@@ -214,6 +213,13 @@ __global__ __launch_bounds__(256) void constrain_init_kernel(const double* __res
   }
 }
 
+__global__ __launch_bounds__(256) void constrain_init_kernel(const double* __restrict__ x_old,
+                                                              const double* __restrict__ xs,
+                                                              Bufs b, int N, double hstar,
+                                                              double a, DevState* st) {
+  constrain_init_body(blockIdx.x, x_old, xs, b, N, hstar, a, st);
+}
+
 // Far-field coefficients (R >= 2a) of an RPY block, and 1/R; the same
 // arithmetic as rpy_coeffs_fast.
 __device__ __forceinline__ void rpy_far_coeffs(double R2, const RpyConst& k, double& cI,
@@ -251,17 +257,17 @@ __device__ __forceinline__ void rpy_near_coeffs(double R2, double y, const RpyCo
 constexpr int kMvThreads = 1024;
 constexpr int kMvWaves = kMvThreads / 64;
 
-__global__ __launch_bounds__(kMvThreads) void dmatvec_kernel(const double* __restrict__ x,
-                                                       const double* __restrict__ f,
-                                                       double* __restrict__ r, int N, RpyConst kc,
-                                                       const DevState* __restrict__ st) {
+__device__ __forceinline__ void dmatvec_body(int bx, const double* __restrict__ x,
+                                             const double* __restrict__ f, double* __restrict__ r,
+                                             int N, const RpyConst& kc,
+                                             const DevState* __restrict__ st) {
   if (st->done) return;
   constexpr int kChunk = 2048;  // beads j staged in LDS per round (96 KB: one workgroup per CU)
   __shared__ double sx[3 * kChunk], sf[3 * kChunk];
   __shared__ double red[kMvWaves][3][kMvI];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int il = lane & 15, jp = lane >> 4;
-  const int i = blockIdx.x * kMvI + il;
+  const int i = bx * kMvI + il;
   const int ii = (i < N) ? i : N - 1;
   const double xi0 = x[3 * ii], xi1 = x[3 * ii + 1], xi2 = x[3 * ii + 2];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -328,11 +334,18 @@ __global__ __launch_bounds__(kMvThreads) void dmatvec_kernel(const double* __res
   __syncthreads();
   if (tid < 3 * kMvI) {
     const int al = tid / kMvI, b = tid % kMvI;
-    const int ib = blockIdx.x * kMvI + b;
+    const int ib = bx * kMvI + b;
     double acc = 0.0;
     for (int q = 0; q < kMvWaves; ++q) acc += red[q][al][b];
     if (ib < N) r[3 * ib + al] = acc;
   }
+}
+
+__global__ __launch_bounds__(kMvThreads) void dmatvec_kernel(const double* __restrict__ x,
+                                                       const double* __restrict__ f,
+                                                       double* __restrict__ r, int N, RpyConst kc,
+                                                       const DevState* __restrict__ st) {
+  dmatvec_body(blockIdx.x, x, f, r, N, kc, st);
 }
 
 // ------------------------------------------------------------ controller
@@ -478,7 +491,7 @@ __device__ void rod_forces(const double* z, const double* __restrict__ u,
 // triangular solve) in LDS and each thread's share of the Krylov vector in
 // registers (unknowns k = tid + kCtlThreads q): global memory is touched only
 // by batches of independent loads and by the stores of the next state.
-__global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
+__device__ __forceinline__ void newton_controller_body(
     Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, double dt,
     double bl, double tol, int maxit, DevState* __restrict__ st) {
   __shared__ double pa[kPadRods], pb[kPadRods], pc[kPadRods], pd[kPadRods];
@@ -796,6 +809,34 @@ __global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
   }
 }
 
+__global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
+    Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, double dt,
+    double bl, double tol, int maxit, DevState* __restrict__ st) {
+  newton_controller_body(b, xs, T_out, N, dt, bl, tol, maxit, st);
+}
+
+// Ensembles: chain blockIdx.z of the table, its workspace carved in place;
+// grids cover the largest chain.
+__global__ __launch_bounds__(256) void constrain_init_batched_kernel(
+    const ChainDesc* __restrict__ cd) {
+  const ChainDesc& c = cd[blockIdx.z];
+  constrain_init_body(blockIdx.x, c.x, c.xs, carve(c.cons, c.N), c.N, c.hstar, c.a, c.st);
+}
+
+__global__ __launch_bounds__(kMvThreads) void dmatvec_batched_kernel(
+    const ChainDesc* __restrict__ cd) {
+  const ChainDesc& c = cd[blockIdx.z];
+  if ((int)blockIdx.x * kMvI >= c.N) return;
+  const Bufs b = carve(c.cons, c.N);
+  dmatvec_body(blockIdx.x, c.x, b.f, b.r, c.N, rpy_const(c.hstar, c.a), c.st);
+}
+
+__global__ __launch_bounds__(kCtlThreads) void newton_controller_batched_kernel(
+    const ChainDesc* __restrict__ cd) {
+  const ChainDesc& c = cd[blockIdx.z];
+  newton_controller_body(carve(c.cons, c.N), c.xs, nullptr, c.N, c.dt, c.b, c.tol, c.maxit, c.st);
+}
+
 }  // namespace
 
 size_t constrain_workspace_bytes(int64_t n_beads) { return carve_bytes((int)n_beads); }
@@ -842,6 +883,53 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
   }
   if (pairs_hint && host_state->done)
     *pairs_hint = host_state->newton_iters + host_state->krylov_iters;
+  return hipGetLastError();
+}
+
+hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads,
+                                    int newton_maxit, DevState* st, DevState* host_states,
+                                    int* pairs_hint) {
+  const int M = max_beads - 1;
+  int iblk = (M + 255) / 256;
+  if (iblk < 16) iblk = 16;
+  BD_LAUNCH("constrain_init_batched", constrain_init_batched_kernel, dim3(iblk, 1, count),
+            dim3(256), 0, s, cd);
+  BD_LAUNCH("newton_controller_batched", newton_controller_batched_kernel, dim3(1, 1, count),
+            dim3(kCtlThreads), 0, s, cd);
+  const dim3 mvgrid((max_beads + kMvI - 1) / kMvI, 1, count);
+  // As for one chain: (matvec, controller) pairs in batches, the first sized
+  // from the previous call, until every chain's iteration has finished;
+  // launches for a finished chain return at once.
+  const int cap = (newton_maxit + 1) * (kKmax + 2);
+  int batch = (pairs_hint && *pairs_hint > 0) ? *pairs_hint + 1 : 8;
+  int launched = 0;
+  bool all_done = false;
+  while (launched < cap) {
+    if (batch > cap - launched) batch = cap - launched;
+    for (int q = 0; q < batch; ++q) {
+      BD_LAUNCH("dmatvec_batched", dmatvec_batched_kernel, mvgrid, dim3(kMvThreads), 0, s, cd);
+      BD_LAUNCH("newton_controller_batched", newton_controller_batched_kernel, dim3(1, 1, count),
+                dim3(kCtlThreads), 0, s, cd);
+    }
+    launched += batch;
+    hipError_t e = hipMemcpyAsync(host_states, st, sizeof(DevState) * (size_t)count,
+                                  hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    all_done = true;
+    for (int c = 0; c < count && all_done; ++c) all_done = host_states[c].done != 0;
+    if (all_done) break;
+    batch = 4;
+  }
+  if (pairs_hint && all_done) {
+    int most = 0;
+    for (int c = 0; c < count; ++c) {
+      const int p = host_states[c].newton_iters + host_states[c].krylov_iters;
+      if (p > most) most = p;
+    }
+    *pairs_hint = most;
+  }
   return hipGetLastError();
 }
 

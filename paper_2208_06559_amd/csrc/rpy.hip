@@ -16,12 +16,11 @@ namespace {
 
 constexpr int kRpyThreads = 256;
 
-__global__ __launch_bounds__(kRpyThreads) void rpy_assemble_kernel(
-    const double* __restrict__ x, double* __restrict__ D, int64_t ld, int N, double hstar,
-    double a, int fill_full) {
-  const int j = blockIdx.y;                         // column bead
-  const int i = blockIdx.x * kRpyThreads + threadIdx.x;  // row bead
-  if (!fill_full && (blockIdx.x + 1) * kRpyThreads <= j) return;  // block entirely above
+__device__ __forceinline__ void rpy_assemble_body(int bx, int j, const double* __restrict__ x,
+                                                  double* __restrict__ D, int64_t ld, int N,
+                                                  double hstar, double a, int fill_full) {
+  const int i = bx * kRpyThreads + threadIdx.x;  // row bead; j is the column bead
+  if (!fill_full && (bx + 1) * kRpyThreads <= j) return;  // block entirely above
   if (i >= N) return;
   if (!fill_full && i < j) return;
   double blk[3][3];
@@ -55,6 +54,21 @@ __global__ __launch_bounds__(kRpyThreads) void rpy_assemble_kernel(
   }
 }
 
+__global__ __launch_bounds__(kRpyThreads) void rpy_assemble_kernel(
+    const double* __restrict__ x, double* __restrict__ D, int64_t ld, int N, double hstar,
+    double a, int fill_full) {
+  rpy_assemble_body(blockIdx.x, blockIdx.y, x, D, ld, N, hstar, a, fill_full);
+}
+
+// Ensembles: chain blockIdx.z, lower triangle; the grid covers the largest chain.
+__global__ __launch_bounds__(kRpyThreads) void rpy_assemble_batched_kernel(
+    const ChainDesc* __restrict__ cd) {
+  const ChainDesc& c = cd[blockIdx.z];
+  const int N = c.N;
+  if ((int)blockIdx.y >= N || (int)blockIdx.x * kRpyThreads >= N) return;
+  rpy_assemble_body(blockIdx.x, blockIdx.y, c.x, c.D, c.ld, N, c.hstar, c.a, 0);
+}
+
 }  // namespace
 
 hipError_t launch_rpy_assemble(hipStream_t s, const bd_params_t& p, const double* x, double* D,
@@ -63,6 +77,13 @@ hipError_t launch_rpy_assemble(hipStream_t s, const bd_params_t& p, const double
   dim3 grid((N + kRpyThreads - 1) / kRpyThreads, N);
   BD_LAUNCH("rpy_assemble", rpy_assemble_kernel, grid, dim3(kRpyThreads), 0, s, x, D, ld, N, p.hstar,
                      p.a, fill == BD_FILL_FULL ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_rpy_assemble_batched(hipStream_t s, const ChainDesc* cd, int count,
+                                       int max_beads) {
+  dim3 grid((max_beads + kRpyThreads - 1) / kRpyThreads, max_beads, count);
+  BD_LAUNCH("rpy_assemble_batched", rpy_assemble_batched_kernel, grid, dim3(kRpyThreads), 0, s, cd);
   return hipGetLastError();
 }
 

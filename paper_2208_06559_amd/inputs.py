@@ -100,4 +100,28 @@ ENSEMBLE_SHEAR = Workload("ensemble 256 chains N in [64,1024] shear Wi=10", 64, 
 LONG_UNIAXIAL = Workload("single-chain N=4096 uniaxial Wi=5", 4096, 5e-5, 200, "uniaxial", 5.0, seed=4)
 GRAD_PLANAR = Workload("64 chains N=256 planar", 256, 1e-4, 200, "planar", 1.0, seed=5, chains=64)
 
+
+
+def ensemble_sizes(count: int, lo: int = 64, hi: int = 1024, seed: int = 3) -> np.ndarray:
+    """Bead counts of an ensemble with uneven chains: N_c = lo + floor((hi -
+    lo + 1) u_c), u_c uniform on [0, 1) from numpy's PCG64 seeded with
+    (seed, 0xC3)."""
+    rng = np.random.default_rng([int(seed), 0xC3])
+    u = rng.random(count)
+    return (lo + np.floor((hi - lo + 1) * u)).astype(np.int64)
+
+
+def ensemble_chains(w: "Workload", sizes) -> list[dict]:
+    """The chains of an ensemble workload with the given bead counts: chain
+    c has N_c beads, the workload's flow at Weissenberg number wi with its
+    own rate wi / lambda(N_c), a random-walk start drawn with (seed, c), and
+    Philox key (seed, c)."""
+    out = []
+    for c, nb in enumerate(int(v) for v in sizes):
+        rate = 0.0 if w.flow == "none" else w.wi / relaxation_time(nb)
+        out.append(dict(n_beads=nb, kappa=kappa_for(w.flow, rate), seed=w.seed, chain_id=c,
+                        x=random_walk(nb, w.b, w.seed, c)))
+    return out
+
+
 WORKLOADS = {w.name: w for w in (SINGLE_SMALL, SINGLE_PLANAR, ENSEMBLE_SHEAR, LONG_UNIAXIAL, GRAD_PLANAR)}

@@ -44,6 +44,20 @@ def test_workspace_size_host_only():
         raise AssertionError("expected BD_ERR_PARAM")
 
 
+def test_ensemble_workspace_size_host_only():
+    ps = [B.make_params(n) for n in (2, 64, 1024)]
+    total = B.ensemble_workspace_size(ps, B.PREC_FP64)
+    assert total >= sum(9 * n * n * 8 for n in (2, 64, 1024))
+    assert B.ensemble_workspace_size(ps, B.PREC_MIXED) > total
+    for bad, status in (([B.make_params(4098)], B.ERR_UNSUPPORTED), ([], B.ERR_PARAM)):
+        try:
+            B.ensemble_workspace_size(bad)
+        except B.BdError as e:
+            assert e.status == status
+        else:
+            raise AssertionError("expected an error")
+
+
 def test_params_struct_layout():
     assert C.sizeof(B.Params) == 4 + 4 + 8 * 4 + 8 * 9 + 8 + 8 + 8 + 4 + 4
     assert C.sizeof(B.Info) == 40

@@ -40,6 +40,16 @@ def cemu(tmp_path_factory):
     return _build(tmp_path_factory, "constrain_emu")
 
 
+@pytest.fixture(scope="module")
+def bemu(tmp_path_factory):
+    return _build(tmp_path_factory, "chol_batch_emu")
+
+
+@pytest.fixture(scope="module")
+def cbemu(tmp_path_factory):
+    return _build(tmp_path_factory, "constrain_batch_emu")
+
+
 CASES = [(n, ld_pad) for n in (1, 6, 127, 128, 129, 256, 257, 383, 640, 1101, 3003) for ld_pad in (0, 3)]
 
 
@@ -67,3 +77,25 @@ def test_constrain_accesses_in_bounds(cemu, N, maxit, skip):
                        timeout=300)
     assert r.returncode == 0, (N, maxit, skip, r.stderr[-3000:])
     assert "status 0" in r.stdout
+
+
+# Ensembles: chains of uneven sizes (one panel or less, ragged last panels,
+# exact multiples of the step) factored in shared launches, each chain in
+# its own exact-size buffers; and the batched tension solve.
+BATCH_SIZES = ["3", "6", "384", "129", "257", "640", "128", "255", "1101"]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("lookahead", [0, 1])
+def test_batched_cholesky_accesses_in_bounds(bemu, prec, lookahead):
+    r = subprocess.run([bemu, str(prec), str(lookahead), *BATCH_SIZES], capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 0, (prec, lookahead, r.stderr[-3000:])
+    assert "status 0" in r.stdout
+
+
+def test_batched_constrain_accesses_in_bounds(cbemu):
+    r = subprocess.run([cbemu, "2", "2", "3", "37", "300", "17", "64"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    assert "status 0" in r.stdout and "done 6" in r.stdout
