@@ -205,6 +205,7 @@ def ensemble_leg(B, I, torch, np, precs, args, dev) -> dict:
             "ms_per_step": ms,
             "cholesky_equiv_tflops": flops / (ms * 1e-3) / 1e12,
             "kernel_ms_per_step": {k: v[1] for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])},
+            "kernel_launches_per_step": {k: v[0] for k, v in prof.items()},
             "cholesky_kernels_ms_per_step": sum(v[1] for v in chol.values()),
             "max_newton_iters": max(i["newton_iters"] for i in infos),
             "max_rod_err": max(i["max_rod_err"] for i in infos),

@@ -63,7 +63,7 @@ struct StepLayout {
   size_t d, chol, brown, cons, y, xs, total;
 };
 
-// batched: the layout of one chain of an ensemble (two-panel Cholesky steps)
+// batched: the layout of one chain of an ensemble
 StepLayout step_layout(int64_t n, bd_precision_t prec, bool batched = false) {
   StepLayout L;
   size_t off = 0;
@@ -157,6 +157,11 @@ struct bd_ensemble_s {
   DevState* st;                      // device, one per chain in the caller's order
   DevState* host_st;                 // pinned mirror
   int pairs_hint;
+  int step_panels;                   // Cholesky panels per step (2 or 4)
+  int32_t* mv_prefix;                // device: flattened matrix-free product grid
+  int mv_blocks;
+  bd::BatchTables tb;                // flattened grids of the factorisation
+  int32_t* tb_dev;                   // device copy of tb.host
 };
 
 extern "C" {
@@ -407,6 +412,8 @@ bd_status_t bd_ensemble_workspace_size(int32_t n_chains, const bd_params_t* p,
 
 static void ensemble_release(bd_ensemble_s* e) {
   if (e->cd) (void)hipFree(e->cd);
+  if (e->mv_prefix) (void)hipFree(e->mv_prefix);
+  if (e->tb_dev) (void)hipFree(e->tb_dev);
   if (e->st) (void)hipFree(e->st);
   if (e->host_st) (void)hipHostFree(e->host_st);
   delete e;
@@ -435,10 +442,16 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
   e->st = nullptr;
   e->host_st = nullptr;
   e->pairs_hint = 0;
+  e->mv_prefix = nullptr;
+  e->mv_blocks = 0;
+  e->tb_dev = nullptr;
+  const char* ep = getenv("BDRPY_ENS_PANELS");
+  e->step_panels = (ep && ep[0] == '4') ? 4 : 2;
   if (hipMalloc(&e->cd, sizeof(bd::ChainDesc) * (size_t)n_chains) != hipSuccess ||
       hipMalloc(&e->st, sizeof(DevState) * (size_t)n_chains) != hipSuccess ||
       hipHostMalloc(&e->host_st, sizeof(DevState) * (size_t)n_chains, hipHostMallocDefault) !=
-          hipSuccess) {
+          hipSuccess ||
+      hipMalloc(&e->mv_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess) {
     ensemble_release(e);
     return BD_ERR_ALLOC;
   }
@@ -477,7 +490,7 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
     if (prec == BD_PREC_MIXED) {
       char* pc = base + L.chol + bd::align_up(sizeof(double) * bd::kNB * bd::kNB, 256);
       d.P32[0] = reinterpret_cast<float*>(pc);
-      d.P32[1] = reinterpret_cast<float*>(pc + bd::align_up(sizeof(float) * (size_t)n * 2 * bd::kNB, 256));
+      d.P32[1] = reinterpret_cast<float*>(pc + bd::align_up(sizeof(float) * (size_t)n * bd::kMaxStep, 256));
     }
     d.xi = reinterpret_cast<double*>(base + L.brown);
     d.part = reinterpret_cast<double*>(base + L.brown + bd::align_up(sizeof(double) * n, 256));
@@ -495,8 +508,34 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
   std::stable_sort(e->host.begin(), e->host.end(),
                    [](const bd::ChainDesc& a, const bd::ChainDesc& b) { return a.n > b.n; });
   memset(e->host_st, 0, sizeof(DevState) * (size_t)n_chains);
+  std::vector<int32_t> prefix((size_t)n_chains + 1, 0);
+  for (int32_t c = 0; c < n_chains; ++c)
+    prefix[(size_t)c + 1] = prefix[(size_t)c] + bd::constrain_mv_blocks(e->host[(size_t)c].N);
+  e->mv_blocks = prefix[(size_t)n_chains];
+  // record the factorisation's flattened grids (no launches), then upload
+  e->tb.record = true;
+  hipError_t rec = hipSuccess;
+  try {
+    rec = bd::launch_cholesky_batched(h->stream, h->aux, h->ev, e->cd, e->host.data(), n_chains,
+                                      prec, e->step_panels, &e->tb);
+  } catch (...) {
+    ensemble_release(e);
+    return BD_ERR_ALLOC;
+  }
+  e->tb.record = false;
+  if (rec != hipSuccess ||
+      hipMalloc(&e->tb_dev, sizeof(int32_t) * (e->tb.host.size() + 1)) != hipSuccess) {
+    ensemble_release(e);
+    return rec != hipSuccess ? BD_ERR_PARAM : BD_ERR_ALLOC;
+  }
+  e->tb.dev = e->tb_dev;
   if (hipMemcpy(e->cd, e->host.data(), sizeof(bd::ChainDesc) * (size_t)n_chains,
                 hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(e->mv_prefix, prefix.data(), sizeof(int32_t) * prefix.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      (!e->tb.host.empty() &&
+       hipMemcpy(e->tb_dev, e->tb.host.data(), sizeof(int32_t) * e->tb.host.size(),
+                 hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemcpy(e->st, e->host_st, sizeof(DevState) * (size_t)n_chains, hipMemcpyHostToDevice) !=
           hipSuccess) {
     ensemble_release(e);
@@ -520,12 +559,13 @@ bd_status_t bd_ensemble_step(bd_ensemble_t e, int64_t step) {
   hipError_t he = hipGetLastError();
   if (he == hipSuccess) he = bd::launch_rpy_assemble_batched(s, e->cd, z, e->max_beads);
   if (he == hipSuccess)
-    he = bd::launch_cholesky_batched(s, h->aux, h->ev, e->cd, e->host.data(), z, e->prec);
+    he = bd::launch_cholesky_batched(s, h->aux, h->ev, e->cd, e->host.data(), z, e->prec,
+                                     e->step_panels, &e->tb);
   if (he == hipSuccess) he = bd::launch_brownian_batched(s, e->cd, z, max_n, step);
   if (he == hipSuccess) he = bd::launch_predictor_batched(s, e->cd, z, e->max_beads);
   if (he == hipSuccess)
-    he = bd::launch_constrain_batched(s, e->cd, z, e->max_beads, e->newton_maxit, e->st,
-                                      e->host_st, &e->pairs_hint);
+    he = bd::launch_constrain_batched(s, e->cd, z, e->max_beads, e->mv_prefix, e->mv_blocks,
+                                      e->newton_maxit, e->st, e->host_st, &e->pairs_hint);
   if (he == hipSuccess) {
     BD_LAUNCH("commit_positions_batched", commit_positions_batched_kernel,
               dim3((unsigned)((max_n + 255) / 256), 1, z), dim3(256), 0, s, e->cd);

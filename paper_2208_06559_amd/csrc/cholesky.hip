@@ -1131,8 +1131,8 @@ __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict_
 
 // ------------------------------------------------------------------------
 // 4. Ensembles: the same kernels over a table of chains, chain blockIdx.z.
-//    The host schedule is common to every chain (two-panel steps from
-//    column 0); each workgroup derives its chain's panel width, row count
+//    The host schedule is common to every chain (steps of a fixed number
+//    of panels from column 0); each workgroup derives its chain's panel width, row count
 //    and tile set from the chain's n and returns at once where the chain
 //    has no work.  Grids cover the largest chain still active.
 // ------------------------------------------------------------------------
@@ -1143,38 +1143,54 @@ __global__ __launch_bounds__(256) void potrf_tile_batched_kernel(const ChainDesc
   potrf_tile_body(c.D, c.ld, k, (c.n - k < NB) ? (int)(c.n - k) : NB, c.W, c.st);
 }
 
-// Panel kp of the step starting at k0, whose FP32 copy (MIXED) is P32[pidx].
+// Panel kp of the step starting at k0, whose FP32 copy (MIXED) is P32[pidx];
+// one flattened grid over every chain's row blocks.
 __global__ __launch_bounds__(kPsThreads) void panel_solve_batched_kernel(
-    const ChainDesc* __restrict__ cd, int64_t k0, int64_t kp, int pidx) {
-  const ChainDesc& c = cd[blockIdx.z];
+    const ChainDesc* __restrict__ cd, const int32_t* __restrict__ prefix, int z, int64_t k0,
+    int64_t kp, int pidx) {
+  const int ci = find_chain(prefix, z, blockIdx.x);
+  const ChainDesc& c = cd[ci];
   const int64_t m = c.n - kp - NB;
-  if (m <= 0 || (int64_t)blockIdx.x * kRB >= m) return;
   float* P = c.P32[pidx];
   if (P) P += (kp - k0) * c.n + kp + NB;
-  panel_solve_body(blockIdx.x, c.D, c.ld, kp, NB, m, c.W, P, c.n);
+  panel_solve_body(blockIdx.x - prefix[ci], c.D, c.ld, kp, NB, m, c.W, P, c.n);
+}
+
+// Tiles of tile set `tiles` in an m x m trailing matrix with TS x TS tiles;
+// nnext: the tile columns updated ahead (at most nnext_panels panels).
+__host__ __device__ inline int64_t syrk_tile_count(int64_t m, int ts, int tiles,
+                                                   int nnext_panels, int64_t* nnext_out) {
+  if (m <= 0) {
+    *nnext_out = 0;
+    return 0;
+  }
+  const int64_t mt = (m + ts - 1) / ts;
+  int64_t np = (m + NB - 1) / NB;
+  if (np > nnext_panels) np = nnext_panels;
+  int64_t nnext = np * (NB / ts);
+  if (nnext > mt) nnext = mt;
+  *nnext_out = nnext;
+  if (tiles == kTilesAll) return mt * (mt + 1) / 2;
+  if (tiles == kTilesNext) return nnext * mt - nnext * (nnext - 1) / 2;
+  return (mt - nnext) * (mt - nnext + 1) / 2;
 }
 
 // Tile set `tiles` of the update of the trailing matrix from row r0 by the
 // kdim columns from k0; nnext_panels caps the panels of the chain's next
 // step (the tile columns updated ahead).
+// One flattened grid over every chain's tiles, each XCD taking a contiguous
+// range of (chain, tile).
 template <typename T, int TS>
 __global__ __launch_bounds__(256, 2) void syrk_update_batched_kernel(
-    const ChainDesc* __restrict__ cd, int64_t k0, int64_t r0, int kdim, int tiles,
-    int nnext_panels, int pidx) {
-  const ChainDesc& c = cd[blockIdx.z];
+    const ChainDesc* __restrict__ cd, const int32_t* __restrict__ prefix, int z, int64_t k0,
+    int64_t r0, int kdim, int tiles, int nnext_panels, int pidx) {
+  const int tg = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int ci = find_chain(prefix, z, tg);
+  const ChainDesc& c = cd[ci];
   const int64_t m = c.n - r0;
-  if (m <= 0) return;
-  const int64_t mt = (m + TS - 1) / TS;
-  int64_t np = (m + NB - 1) / NB;
-  if (np > nnext_panels) np = nnext_panels;
-  int64_t nnext = np * (NB / TS);
-  if (nnext > mt) nnext = mt;
-  int64_t nt = 0;
-  if (tiles == kTilesAll) nt = mt * (mt + 1) / 2;
-  if (tiles == kTilesNext) nt = nnext * mt - nnext * (nnext - 1) / 2;
-  if (tiles == kTilesRest) nt = (mt - nnext) * (mt - nnext + 1) / 2;
-  const int t = xcd_contiguous(blockIdx.x, gridDim.x);
-  if (t >= nt) return;
+  int64_t nnext;
+  (void)syrk_tile_count(m, TS, tiles, nnext_panels, &nnext);
+  const int t = tg - prefix[ci];
   const T* L;
   int64_t ldl;
   if constexpr (sizeof(T) == 4) {
@@ -1191,7 +1207,7 @@ __global__ __launch_bounds__(256, 2) void syrk_update_batched_kernel(
 
 size_t cholesky_batched_workspace_bytes(int64_t n, bd_precision_t prec) {
   size_t b = align_up(sizeof(double) * NB * NB, 256);
-  if (prec == BD_PREC_MIXED) b += 2 * align_up(sizeof(float) * (size_t)n * 2 * NB, 256);
+  if (prec == BD_PREC_MIXED) b += 2 * align_up(sizeof(float) * (size_t)n * kMaxStep, 256);
   return b;
 }
 
@@ -1384,9 +1400,31 @@ struct BatchCtx {
   const ChainDesc* host;     // its host copy
   int count;
   bool mixed;
+  int64_t step;  // columns per step, the same for every chain
+  BatchTables* tb;
 };
 
-constexpr int64_t kBatchStep = 2 * NB;  // two panels per step for every chain
+// The prefix array of the next launch from the workgroup counts of chains
+// 0 .. z-1 (recorded, or checked against the recording); *total: the grid.
+// Returns the device copy (null while recording).
+template <typename F>
+const int32_t* flat_table(const BatchCtx& b, int z, F count, int* total, bool* ok) {
+  BatchTables& t = *b.tb;
+  const size_t off = t.cur;
+  int64_t acc = 0;
+  *ok = true;
+  if (t.record) t.host.push_back(0);
+  else if (off + (size_t)z >= t.host.size() || t.host[off] != 0) *ok = false;
+  for (int c = 0; c < z; ++c) {
+    acc += count(c);
+    if (acc > INT32_MAX) *ok = false;
+    if (t.record) t.host.push_back((int32_t)acc);
+    else if (*ok && t.host[off + (size_t)c + 1] != (int32_t)acc) *ok = false;
+  }
+  t.cur += (size_t)z + 1;
+  *total = (int)acc;
+  return t.record ? nullptr : t.dev + off;
+}
 
 // Chains with n > k.
 int active(const BatchCtx& b, int64_t k) {
@@ -1395,57 +1433,59 @@ int active(const BatchCtx& b, int64_t k) {
   return a;
 }
 
-int batch_pidx(int64_t k0) { return (int)((k0 / kBatchStep) & 1); }
+int batch_pidx(const BatchCtx& b, int64_t k0) { return (int)((k0 / b.step) & 1); }
 
 hipError_t batch_trailing(const BatchCtx& b, hipStream_t s, int64_t k0, int64_t r0, int kdim,
                           int tiles, int nnext_panels) {
   const int z = active(b, r0);
   if (z == 0) return hipSuccess;
   const int ts = (tiles == kTilesNext) ? kTS / 2 : kTS;
-  // grid for the largest chain (the first of the table)
-  const int64_t m = b.host[0].n - r0;
-  const int64_t mt = (m + ts - 1) / ts;
-  int64_t np = (m + NB - 1) / NB;
-  if (np > nnext_panels) np = nnext_panels;
-  int64_t nnext = np * (NB / ts);
-  if (nnext > mt) nnext = mt;
-  int64_t nt = 0;
-  if (tiles == kTilesAll) nt = mt * (mt + 1) / 2;
-  if (tiles == kTilesNext) nt = nnext * mt - nnext * (nnext - 1) / 2;
-  if (tiles == kTilesRest) nt = (mt - nnext) * (mt - nnext + 1) / 2;
-  if (nt <= 0) return hipSuccess;
-  const dim3 grid((unsigned)nt, 1, z);
-  const int pidx = batch_pidx(k0);
+  int total = 0;
+  bool ok = true;
+  const int32_t* pre = flat_table(b, z, [&](int c) {
+    int64_t nn;
+    return syrk_tile_count(b.host[c].n - r0, ts, tiles, nnext_panels, &nn);
+  }, &total, &ok);
+  if (!ok) return hipErrorInvalidValue;
+  if (total == 0 || b.tb->record) return hipSuccess;
+  const dim3 grid((unsigned)total);
+  const int pidx = batch_pidx(b, k0);
   if (b.mixed && ts == kTS)
     BD_LAUNCH("syrk_update_f32_batched", (syrk_update_batched_kernel<float, kTS>), grid, dim3(256),
-              0, s, b.cd, k0, r0, kdim, tiles, nnext_panels, pidx);
+              0, s, b.cd, pre, z, k0, r0, kdim, tiles, nnext_panels, pidx);
   else if (b.mixed)
     BD_LAUNCH("syrk_next_f32_batched", (syrk_update_batched_kernel<float, kTS / 2>), grid,
-              dim3(256), 0, s, b.cd, k0, r0, kdim, tiles, nnext_panels, pidx);
+              dim3(256), 0, s, b.cd, pre, z, k0, r0, kdim, tiles, nnext_panels, pidx);
   else if (ts == kTS)
     BD_LAUNCH("syrk_update_f64_batched", (syrk_update_batched_kernel<double, kTS>), grid,
-              dim3(256), 0, s, b.cd, k0, r0, kdim, tiles, nnext_panels, pidx);
+              dim3(256), 0, s, b.cd, pre, z, k0, r0, kdim, tiles, nnext_panels, pidx);
   else
     BD_LAUNCH("syrk_next_f64_batched", (syrk_update_batched_kernel<double, kTS / 2>), grid,
-              dim3(256), 0, s, b.cd, k0, r0, kdim, tiles, nnext_panels, pidx);
+              dim3(256), 0, s, b.cd, pre, z, k0, r0, kdim, tiles, nnext_panels, pidx);
   return hipGetLastError();
 }
 
 hipError_t batch_factor_step(const BatchCtx& b, hipStream_t s, int64_t k0) {
   hipError_t e;
-  for (int64_t kp = k0; kp < k0 + kBatchStep; kp += NB) {
+  for (int64_t kp = k0; kp < k0 + b.step; kp += NB) {
     const int z = active(b, kp);
     if (z == 0) break;
     if (kp > k0 && (e = batch_trailing(b, s, k0, kp, (int)(kp - k0), kTilesNext, 1)) != hipSuccess)
       return e;
-    BD_LAUNCH("potrf_tile_batched", potrf_tile_batched_kernel, dim3(1, 1, z), dim3(256), 0, s,
-              b.cd, kp);
+    if (!b.tb->record)
+      BD_LAUNCH("potrf_tile_batched", potrf_tile_batched_kernel, dim3(1, 1, z), dim3(256), 0, s,
+                b.cd, kp);
     const int zp = active(b, kp + NB);  // chains whose panel has rows below it
     if (zp > 0) {
-      const int64_t m = b.host[0].n - kp - NB;
-      BD_LAUNCH("panel_solve_batched", panel_solve_batched_kernel,
-                dim3((unsigned)((m + kRB - 1) / kRB), 1, zp), dim3(kPsThreads), 0, s, b.cd, k0,
-                kp, batch_pidx(k0));
+      int total = 0;
+      bool ok = true;
+      const int32_t* pre = flat_table(b, zp, [&](int c) {
+        return (b.host[c].n - kp - NB + kRB - 1) / kRB;
+      }, &total, &ok);
+      if (!ok) return hipErrorInvalidValue;
+      if (!b.tb->record)
+        BD_LAUNCH("panel_solve_batched", panel_solve_batched_kernel, dim3((unsigned)total),
+                  dim3(kPsThreads), 0, s, b.cd, pre, zp, k0, kp, batch_pidx(b, k0));
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -1454,15 +1494,17 @@ hipError_t batch_factor_step(const BatchCtx& b, hipStream_t s, int64_t k0) {
 
 }  // namespace
 
-// launch_cholesky's lookahead schedule, two panels per step, over every
-// chain of the table at once.
+// launch_cholesky's lookahead schedule, `panels` panels per step, over
+// every chain of the table at once.
 hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev[4],
                                    const ChainDesc* cd, const ChainDesc* cd_host, int count,
-                                   bd_precision_t prec) {
+                                   bd_precision_t prec, int panels, BatchTables* tb) {
   if (count <= 0) return hipSuccess;
-  BatchCtx b{cd, cd_host, count, prec == BD_PREC_MIXED};
+  panels = (panels >= 4) ? 4 : 2;
+  BatchCtx b{cd, cd_host, count, prec == BD_PREC_MIXED, (int64_t)panels * NB, tb};
+  tb->cur = 0;
   const int64_t n = cd_host[0].n;  // the largest chain
-  const int64_t w = kBatchStep;
+  const int64_t w = b.step;
   hipError_t e;
   if (!aux) {
     for (int64_t k = 0; k < n; k += w) {
@@ -1472,24 +1514,30 @@ hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev
     }
     return hipGetLastError();
   }
+  // the recording pass takes the same path without launching anything
+  const bool run = !tb->record;
   hipEvent_t ev_fork = ev[0], ev_panel = ev[1], ev_rest = ev[2], ev_next = ev[3];
-  if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
-  if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
+  auto record = [&](hipEvent_t v, hipStream_t q) { return run ? hipEventRecord(v, q) : hipSuccess; };
+  auto wait = [&](hipStream_t q, hipEvent_t v) {
+    return run ? hipStreamWaitEvent(q, v, 0) : hipSuccess;
+  };
+  if ((e = record(ev_fork, s)) != hipSuccess) return e;
+  if ((e = wait(aux, ev_fork)) != hipSuccess) return e;
   if ((e = batch_factor_step(b, aux, 0)) != hipSuccess) return e;
-  if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
+  if ((e = record(ev_panel, aux)) != hipSuccess) return e;
   for (int64_t k = 0; k + w < n; k += w) {
     const int64_t r0 = k + w;
-    if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
-    if (k > 0 && (e = hipStreamWaitEvent(aux, ev_rest, 0)) != hipSuccess) return e;
-    if ((e = batch_trailing(b, aux, k, r0, (int)w, kTilesNext, 2)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev_next, aux)) != hipSuccess) return e;
+    if ((e = wait(s, ev_panel)) != hipSuccess) return e;
+    if (k > 0 && (e = wait(aux, ev_rest)) != hipSuccess) return e;
+    if ((e = batch_trailing(b, aux, k, r0, (int)w, kTilesNext, panels)) != hipSuccess) return e;
+    if ((e = record(ev_next, aux)) != hipSuccess) return e;
     if ((e = batch_factor_step(b, aux, r0)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s, ev_next, 0)) != hipSuccess) return e;
-    if ((e = batch_trailing(b, s, k, r0, (int)w, kTilesRest, 2)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev_rest, s)) != hipSuccess) return e;
+    if ((e = record(ev_panel, aux)) != hipSuccess) return e;
+    if ((e = wait(s, ev_next)) != hipSuccess) return e;
+    if ((e = batch_trailing(b, s, k, r0, (int)w, kTilesRest, panels)) != hipSuccess) return e;
+    if ((e = record(ev_rest, s)) != hipSuccess) return e;
   }
-  if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
+  if ((e = wait(s, ev_panel)) != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/bdrpy.h"
 
 namespace bd {
@@ -77,7 +79,7 @@ struct ChainDesc {
   double* x;          // N x 3 positions (in the packed array of the ensemble)
   double* D;          // n x ld diffusion tensor, then its factor
   double* W;          // Cholesky: inverses of the diagonal sub-blocks
-  float* P32[2];      // Cholesky MIXED: FP32 panel copies of alternate steps (n x 2 NB)
+  float* P32[2];      // Cholesky MIXED: FP32 panel copies of alternate steps (n x kMaxStep)
   double* xi;         // noise (n)
   double* part;       // TRMV partial sums
   double* y;          // Brownian displacement (n)
@@ -86,15 +88,36 @@ struct ChainDesc {
   DevState* st;       // status of this chain
 };
 
-// Bytes each chain of an ensemble needs in the Cholesky workspace (two-panel
-// steps, so the FP32 panel copies are n x 2 NB).
+// Flattened grids: chain c owns workgroups prefix[c] .. prefix[c+1]-1 of a
+// launch (prefix has count + 1 entries, prefix[0] = 0); returns c for
+// workgroup t by bisection (wave-uniform scalar loads).
+__device__ __forceinline__ int find_chain(const int32_t* __restrict__ prefix, int count, int t) {
+  int lo = 0, hi = count;  // prefix[lo] <= t < prefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Bytes each chain of an ensemble needs in the Cholesky workspace.
 size_t cholesky_batched_workspace_bytes(int64_t n, bd_precision_t prec);
+// Flattened grids of the batched factorisation: one prefix array (chain ->
+// first workgroup) per launch, in launch order.  A recording pass at plan
+// creation builds them on the host (no launches); they are uploaded once
+// and every step reads them back in the same order.
+struct BatchTables {
+  std::vector<int32_t> host;
+  const int32_t* dev = nullptr;
+  size_t cur = 0;
+  bool record = false;
+};
 // The chains of `cd` (device table, `cd_host` its host copy) ordered by
 // decreasing n, `count` of them; every chain is factored in place with the
-// schedule of launch_cholesky at two panels per step.
+// schedule of launch_cholesky at `panels` (2 or 4) panels per step.
 hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev[4],
                                    const ChainDesc* cd, const ChainDesc* cd_host, int count,
-                                   bd_precision_t prec);
+                                   bd_precision_t prec, int panels, BatchTables* tb);
 hipError_t launch_rpy_assemble_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads);
 hipError_t launch_brownian_batched(hipStream_t s, const ChainDesc* cd, int count, int64_t max_n,
                                    int64_t step);
@@ -102,8 +125,11 @@ hipError_t launch_predictor_batched(hipStream_t s, const ChainDesc* cd, int coun
 // Runs the tension solve of every chain; returns once every chain's
 // iteration has finished (polls the `count` states at `st`, which are
 // contiguous, through the pinned `host_states`).
+// mv_prefix: workgroups of the matrix-free product per chain, flattened
+// (constrain_mv_blocks(N) for chain c of the table), mv_blocks in all.
+int constrain_mv_blocks(int n_beads);
 hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads,
-                                    int newton_maxit, DevState* st, DevState* host_states,
-                                    int* pairs_hint);
+                                    const int32_t* mv_prefix, int mv_blocks, int newton_maxit,
+                                    DevState* st, DevState* host_states, int* pairs_hint);
 
 }  // namespace bd

@@ -257,12 +257,14 @@ __device__ __forceinline__ void rpy_near_coeffs(double R2, double y, const RpyCo
 constexpr int kMvThreads = 1024;
 constexpr int kMvWaves = kMvThreads / 64;
 
+// kChunk: beads j staged in LDS per round (2048: 96 KB, one workgroup per
+// CU; 1024: two workgroups per CU, for the ensembles' shorter chains).
+template <int kChunk>
 __device__ __forceinline__ void dmatvec_body(int bx, const double* __restrict__ x,
                                              const double* __restrict__ f, double* __restrict__ r,
                                              int N, const RpyConst& kc,
                                              const DevState* __restrict__ st) {
   if (st->done) return;
-  constexpr int kChunk = 2048;  // beads j staged in LDS per round (96 KB: one workgroup per CU)
   __shared__ double sx[3 * kChunk], sf[3 * kChunk];
   __shared__ double red[kMvWaves][3][kMvI];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(kMvThreads) void dmatvec_kernel(const double* __res
                                                        const double* __restrict__ f,
                                                        double* __restrict__ r, int N, RpyConst kc,
                                                        const DevState* __restrict__ st) {
-  dmatvec_body(blockIdx.x, x, f, r, N, kc, st);
+  dmatvec_body<2048>(blockIdx.x, x, f, r, N, kc, st);
 }
 
 // ------------------------------------------------------------ controller
@@ -823,12 +825,14 @@ __global__ __launch_bounds__(256) void constrain_init_batched_kernel(
   constrain_init_body(blockIdx.x, c.x, c.xs, carve(c.cons, c.N), c.N, c.hstar, c.a, c.st);
 }
 
+// One flattened grid over every chain's bead blocks (no idle workgroups).
 __global__ __launch_bounds__(kMvThreads) void dmatvec_batched_kernel(
-    const ChainDesc* __restrict__ cd) {
-  const ChainDesc& c = cd[blockIdx.z];
-  if ((int)blockIdx.x * kMvI >= c.N) return;
+    const ChainDesc* __restrict__ cd, const int32_t* __restrict__ prefix, int count) {
+  const int t = blockIdx.x;
+  const int ci = find_chain(prefix, count, t);
+  const ChainDesc& c = cd[ci];
   const Bufs b = carve(c.cons, c.N);
-  dmatvec_body(blockIdx.x, c.x, b.f, b.r, c.N, rpy_const(c.hstar, c.a), c.st);
+  dmatvec_body<1024>(t - prefix[ci], c.x, b.f, b.r, c.N, rpy_const(c.hstar, c.a), c.st);
 }
 
 __global__ __launch_bounds__(kCtlThreads) void newton_controller_batched_kernel(
@@ -886,9 +890,11 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
   return hipGetLastError();
 }
 
+int constrain_mv_blocks(int n_beads) { return (n_beads + kMvI - 1) / kMvI; }
+
 hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads,
-                                    int newton_maxit, DevState* st, DevState* host_states,
-                                    int* pairs_hint) {
+                                    const int32_t* mv_prefix, int mv_blocks, int newton_maxit,
+                                    DevState* st, DevState* host_states, int* pairs_hint) {
   const int M = max_beads - 1;
   int iblk = (M + 255) / 256;
   if (iblk < 16) iblk = 16;
@@ -896,7 +902,7 @@ hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int coun
             dim3(256), 0, s, cd);
   BD_LAUNCH("newton_controller_batched", newton_controller_batched_kernel, dim3(1, 1, count),
             dim3(kCtlThreads), 0, s, cd);
-  const dim3 mvgrid((max_beads + kMvI - 1) / kMvI, 1, count);
+  const dim3 mvgrid(mv_blocks);
   // As for one chain: (matvec, controller) pairs in batches, the first sized
   // from the previous call, until every chain's iteration has finished;
   // launches for a finished chain return at once.
@@ -907,7 +913,8 @@ hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int coun
   while (launched < cap) {
     if (batch > cap - launched) batch = cap - launched;
     for (int q = 0; q < batch; ++q) {
-      BD_LAUNCH("dmatvec_batched", dmatvec_batched_kernel, mvgrid, dim3(kMvThreads), 0, s, cd);
+      BD_LAUNCH("dmatvec_batched", dmatvec_batched_kernel, mvgrid, dim3(kMvThreads), 0, s, cd,
+                mv_prefix, count);
       BD_LAUNCH("newton_controller_batched", newton_controller_batched_kernel, dim3(1, 1, count),
                 dim3(kCtlThreads), 0, s, cd);
     }

@@ -4,7 +4,7 @@
 // workspace at exactly the documented sizes (matrix (n-1)*ld + n doubles,
 // cholesky_batched_workspace_bytes(n) of workspace), so an access of one
 // chain's kernels outside its own buffers is reported.
-// Usage: chol_batch_emu prec(0 fp64, 1 mixed) lookahead(0|1) n_0 n_1 ...
+// Usage: chol_batch_emu prec(0 fp64, 1 mixed) lookahead(0|1) panels(2|4) n_0 n_1 ...
 #include <algorithm>
 #include <vector>
 
@@ -17,13 +17,13 @@ void prof_mark_end(hipStream_t) {}
 }  // namespace bd
 
 int main(int argc, char** argv) {
-  if (argc < 4) return 2;
-  const int prec = atoi(argv[1]), use_aux = atoi(argv[2]);
-  const int count = argc - 3;
+  if (argc < 5) return 2;
+  const int prec = atoi(argv[1]), use_aux = atoi(argv[2]), panels = atoi(argv[3]);
+  const int count = argc - 4;
   std::vector<bd::ChainDesc> cd((size_t)count);
   std::vector<void*> blocks;
   for (int c = 0; c < count; ++c) {
-    const int64_t n = atoll(argv[3 + c]), ld = n + c % 3;
+    const int64_t n = atoll(argv[4 + c]), ld = n + c % 3;
     bd::ChainDesc& d = cd[(size_t)c];
     memset(&d, 0, sizeof(d));
     d.n = n;
@@ -40,7 +40,7 @@ int main(int argc, char** argv) {
     if (prec == 1) {
       char* pc = ws + bd::align_up(sizeof(double) * bd::kNB * bd::kNB, 256);
       d.P32[0] = (float*)pc;
-      d.P32[1] = (float*)(pc + bd::align_up(sizeof(float) * (size_t)n * 2 * bd::kNB, 256));
+      d.P32[1] = (float*)(pc + bd::align_up(sizeof(float) * (size_t)n * bd::kMaxStep, 256));
     }
     d.st = (bd::DevState*)calloc(1, sizeof(bd::DevState));
     blocks.push_back(d.D);
@@ -50,11 +50,24 @@ int main(int argc, char** argv) {
   std::stable_sort(cd.begin(), cd.end(),
                    [](const bd::ChainDesc& a, const bd::ChainDesc& b) { return a.n > b.n; });
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  const hipError_t e = bd::launch_cholesky_batched(nullptr, use_aux ? (hipStream_t)0x1 : nullptr,
-                                                   ev, cd.data(), cd.data(), count,
-                                                   (bd_precision_t)prec);
-  printf("chains=%d prec=%d lookahead=%d: status %d, %ld launches\n", count, prec, use_aux, e,
-         g_emu_launches);
+  hipStream_t aux = use_aux ? (hipStream_t)0x1 : nullptr;
+  // recording pass, then the run from an exact-size copy of the tables
+  bd::BatchTables tb;
+  tb.record = true;
+  hipError_t e = bd::launch_cholesky_batched(nullptr, aux, ev, cd.data(), cd.data(), count,
+                                             (bd_precision_t)prec, panels, &tb);
+  const long recorded = g_emu_launches;
+  tb.record = false;
+  int32_t* tdev = (int32_t*)malloc(sizeof(int32_t) * (tb.host.size() + 1));
+  memcpy(tdev, tb.host.data(), sizeof(int32_t) * tb.host.size());
+  tb.dev = tdev;
+  if (e == hipSuccess)
+    e = bd::launch_cholesky_batched(nullptr, aux, ev, cd.data(), cd.data(), count,
+                                    (bd_precision_t)prec, panels, &tb);
+  if (recorded != 0 || tb.cur != tb.host.size()) e = hipErrorInvalidValue;
+  free(tdev);
+  printf("chains=%d prec=%d lookahead=%d panels=%d: status %d, %ld launches\n", count, prec,
+         use_aux, panels, e, g_emu_launches);
   for (void* p : blocks) free(p);
   return e != hipSuccess ? 1 : 0;
 }

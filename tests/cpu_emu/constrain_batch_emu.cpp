@@ -55,8 +55,12 @@ int main(int argc, char** argv) {
   }
   std::stable_sort(cd.begin(), cd.end(),
                    [](const bd::ChainDesc& a, const bd::ChainDesc& b) { return a.n > b.n; });
+  std::vector<int32_t> prefix((size_t)count + 1, 0);
+  for (int c = 0; c < count; ++c)
+    prefix[(size_t)c + 1] = prefix[(size_t)c] + bd::constrain_mv_blocks(cd[(size_t)c].N);
   int hint = 0;
-  const hipError_t e = bd::launch_constrain_batched(nullptr, cd.data(), count, max_beads, maxit,
+  const hipError_t e = bd::launch_constrain_batched(nullptr, cd.data(), count, max_beads,
+                                                    prefix.data(), prefix[(size_t)count], maxit,
                                                     st, host, &hint);
   int done = 0;
   for (int c = 0; c < count; ++c) done += host[c].done;

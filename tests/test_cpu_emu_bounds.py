@@ -87,10 +87,11 @@ BATCH_SIZES = ["3", "6", "384", "129", "257", "640", "128", "255", "1101"]
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("lookahead", [0, 1])
-def test_batched_cholesky_accesses_in_bounds(bemu, prec, lookahead):
-    r = subprocess.run([bemu, str(prec), str(lookahead), *BATCH_SIZES], capture_output=True,
-                       text=True, timeout=600)
-    assert r.returncode == 0, (prec, lookahead, r.stderr[-3000:])
+@pytest.mark.parametrize("panels", [2, 4])
+def test_batched_cholesky_accesses_in_bounds(bemu, prec, lookahead, panels):
+    r = subprocess.run([bemu, str(prec), str(lookahead), str(panels), *BATCH_SIZES],
+                       capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, (prec, lookahead, panels, r.stderr[-3000:])
     assert "status 0" in r.stdout
 
 
