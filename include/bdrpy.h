@@ -170,11 +170,14 @@ bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out);
  * p[0..n_chains-1]: per-chain parameters (sizes, flows, seeds may all
  * differ; 1 <= n_chains <= 65535, every N <= 4097).  Positions are packed:
  * chain c is the N_c x 3 block starting at row sum_{c' < c} N_c' of d_x.
- * A step of the ensemble advances every chain exactly as bd_step with the
- * same parameters and `step` would (the same kernels, arithmetic and
- * reduction orders), with two-panel Cholesky steps for every chain; for
- * n <= 4096 that is also bd_step's schedule, so the results are bitwise
- * those of bd_step. */
+ * A step of the ensemble advances every chain as bd_step with the same
+ * parameters and `step` would (the same kernels, arithmetic and reduction
+ * orders) except that every chain's Cholesky takes steps of four panels
+ * (environment BDRPY_ENS_PANELS=2 at creation: two).  bd_step takes
+ * four-panel steps while more than BDRPY_WIDE_ROWS rows remain (read at
+ * bd_create, default 4096) and two after, so with BDRPY_WIDE_ROWS=0 (or
+ * BDRPY_ENS_PANELS=2 and n <= 4096) each chain's result is bitwise that of
+ * bd_step; otherwise the two differ only in rounding order. */
 typedef struct bd_ensemble_s* bd_ensemble_t;
 
 /* Bytes of device workspace for the ensemble p[0..n_chains-1] in `prec`. */

@@ -445,8 +445,11 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
   e->mv_prefix = nullptr;
   e->mv_blocks = 0;
   e->tb_dev = nullptr;
+  // BDRPY_ENS_PANELS=2 takes two-panel factorisation steps (for
+  // comparisons); by default four: with many chains sharing each launch the
+  // trailing updates, not the chain of diagonal blocks, bound the time.
   const char* ep = getenv("BDRPY_ENS_PANELS");
-  e->step_panels = (ep && ep[0] == '4') ? 4 : 2;
+  e->step_panels = (ep && ep[0] == '2') ? 2 : 4;
   if (hipMalloc(&e->cd, sizeof(bd::ChainDesc) * (size_t)n_chains) != hipSuccess ||
       hipMalloc(&e->st, sizeof(DevState) * (size_t)n_chains) != hipSuccess ||
       hipHostMalloc(&e->host_st, sizeof(DevState) * (size_t)n_chains, hipHostMallocDefault) !=

@@ -2,8 +2,10 @@
 launches (the chain is the third grid dimension of every kernel).
 
 * Every chain of an ensemble step equals bd_step on that chain alone,
-  bitwise: the same kernels, arithmetic and reduction orders, and for
-  n <= 4096 the same two-panel factorisation schedule.
+  bitwise: the same kernels, arithmetic and reduction orders and the same
+  factorisation schedule (four-panel steps: bd_step on a handle created
+  with BDRPY_WIDE_ROWS=0; two-panel steps: BDRPY_ENS_PANELS=2 against the
+  default handle, n <= 4096).
 * Against the oracle's step from the same state and seeds, each chain is
   within the single-chain tolerances: FP64 1e-10 b, mixed 1e-6 b, every rod
   length within 1e-10 b.
@@ -14,6 +16,7 @@ launches (the chain is the third grid dimension of every kernel).
   same tolerances.
 """
 import ctypes as C
+import os
 
 import numpy as np
 import pytest
@@ -63,18 +66,49 @@ def _split(xp, chains):
     return out
 
 
+@pytest.fixture(scope="module")
+def h_wide():
+    """A handle whose single-chain factorisations take four-panel steps
+    throughout (the ensembles' default schedule)."""
+    old = os.environ.get("BDRPY_WIDE_ROWS")
+    os.environ["BDRPY_WIDE_ROWS"] = "0"
+    try:
+        hh = B.Handle(0)
+    finally:
+        if old is None:
+            del os.environ["BDRPY_WIDE_ROWS"]
+        else:
+            os.environ["BDRPY_WIDE_ROWS"] = old
+    yield hh
+    hh.close()
+
+
+def _ensemble_with_panels(h, params, xp, prec, panels):
+    old = os.environ.get("BDRPY_ENS_PANELS")
+    os.environ["BDRPY_ENS_PANELS"] = str(panels)
+    try:
+        return B.Ensemble(h, params, xp, prec)
+    finally:
+        if old is None:
+            del os.environ["BDRPY_ENS_PANELS"]
+        else:
+            os.environ["BDRPY_ENS_PANELS"] = old
+
+
+@pytest.mark.parametrize("panels", [4, 2])
 @pytest.mark.parametrize("prec", [B.PREC_FP64, B.PREC_MIXED])
-def test_ensemble_equals_single_chain_bitwise(h, prec):
+def test_ensemble_equals_single_chain_bitwise(h, h_wide, prec, panels):
     chains = _chains(SIZES)
     xp = _packed(chains)
-    ens = B.Ensemble(h, [pg for pg, _, _ in chains], xp, prec)
+    ens = _ensemble_with_panels(h, [pg for pg, _, _ in chains], xp, prec, panels)
+    hs = h_wide if panels == 4 else h
     singles = [torch.tensor(x, dtype=torch.float64, device=DEV) for _, _, x in chains]
     for s in range(3):
         ens.step(s)
         infos = ens.info()
         for c, (pg, _, _) in enumerate(chains):
-            h.step(pg, s, singles[c], prec)
-            st = h.info()
+            hs.step(pg, s, singles[c], prec)
+            st = hs.info()
             assert st == infos[c], (s, c, st, infos[c])
             assert st["status"] == B.OK
         for c, xg in enumerate(_split(xp, chains)):
@@ -121,7 +155,7 @@ W = I.ENSEMBLE_SHEAR
 
 
 @pytest.mark.parametrize("prec,tol", [(B.PREC_FP64, 1e-10), (B.PREC_MIXED, 1e-6)])
-def test_ensemble_full_size(h, prec, tol):
+def test_ensemble_full_size(h, h_wide, prec, tol):
     sizes = I.ensemble_sizes(W.chains, seed=W.seed)
     spec = I.ensemble_chains(W, sizes)
     pgs = [B.make_params(d["n_beads"], dt=W.dt, kappa=d["kappa"], seed=d["seed"],
@@ -139,8 +173,8 @@ def test_ensemble_full_size(h, prec, tol):
     for c in sorted({int(order[0]), int(order[-1]), 17, 200}):
         d = spec[c]
         single = torch.tensor(d["x"], dtype=torch.float64, device=DEV)
-        h.step(pgs[c], 0, single, prec)
-        assert h.info() == infos[c]
+        h_wide.step(pgs[c], 0, single, prec)
+        assert h_wide.info() == infos[c]
         assert torch.equal(single, xs[c]), c
         po = o.make_params(d["n_beads"], dt=W.dt, kappa=d["kappa"], seed=d["seed"],
                            chain_id=d["chain_id"], hstar=W.hstar, a=W.a, b=W.b)
