@@ -13,6 +13,10 @@
  *    infinite-stiffness limit, a tension T_k along the bond direction at the
  *    start of the step, solved implicitly through the full diffusion tensor
  *    (the K* -> infinity limit of the semi-implicit update of Eqs. 13-17).
+ *    bdo_step_fraenkel keeps the paper's finite-stiffness springs and its
+ *    semi-implicit link update instead; there bead 0 moves by its explicit
+ *    equation of motion and the other beads follow along the new links
+ *    (the paper integrates link vectors and is silent on positions).
  *  - The bead radius a is a parameter separate from h* (a = b/2 in every
  *    workload); h* <= a keeps D positive definite.
  *  - Noise is Gaussian by default (covariance 2 dt D); the paper's uniform
@@ -592,6 +596,78 @@ int bdo_step(const bdo_params* p, int64_t step, double* x, bdo_info* info) {
     memcpy(x, xs, sizeof(double) * (size_t)n);
   }
   free(D); free(y); free(xs);
+  if (info) *info = loc;
+  return loc.status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Stiff Fraenkel springs, semi-implicit (Eqs. 3, 13-17).               */
+/* ------------------------------------------------------------------ */
+int bdo_step_fraenkel(const bdo_params* p, double k_spring, int64_t step, double* x,
+                      bdo_info* info) {
+  bdo_info loc;
+  memset(&loc, 0, sizeof loc);
+  if (!params_valid(p) || !x || !(k_spring > 0.0) || !isfinite(k_spring)) {
+    loc.status = BDO_ERR_PARAM;
+    if (info) *info = loc;
+    return BDO_ERR_PARAM;
+  }
+  const int64_t N = p->n_beads, n = 3 * N, M = N - 1;
+  const double dt = p->dt, b = p->b, K = k_spring;
+  double* D = (double*)malloc(sizeof(double) * (size_t)(n * n));
+  double* y = (double*)malloc(sizeof(double) * (size_t)n);
+  double* F = (double*)malloc(sizeof(double) * (size_t)(3 * M));
+  double* f = (double*)malloc(sizeof(double) * (size_t)n);
+  double* v = (double*)malloc(sizeof(double) * (size_t)n);
+  double* Qn = (double*)malloc(sizeof(double) * (size_t)(3 * M));
+  bdo_rpy_assemble(p, x, D, n, BDO_FILL_LOWER);
+  loc.potrf_info = bdo_cholesky(n, D, n);
+  if (loc.potrf_info != 0) {
+    loc.status = BDO_ERR_NOT_SPD;
+  } else {
+    bdo_brownian(p, step, D, n, y, NULL);
+    /* spring forces at t (Eq. 3) and the net force on each bead */
+    for (int64_t k = 0; k < M; ++k) {
+      const double* q = x + 3 * (k + 1);
+      const double Q[3] = {q[0] - x[3 * k], q[1] - x[3 * k + 1], q[2] - x[3 * k + 2]};
+      const double len = sqrt(dot3(Q, Q));
+      for (int al = 0; al < 3; ++al) F[3 * k + al] = K * (len - b) * Q[al] / len;
+    }
+    for (int64_t i = 0; i < N; ++i)
+      for (int al = 0; al < 3; ++al)
+        f[3 * i + al] = (i < M ? F[3 * i + al] : 0.0) - (i > 0 ? F[3 * (i - 1) + al] : 0.0);
+    D_times(p, x, f, v);
+    /* Eq. 14, then the closed form of Eqs. 15-17 per link */
+    double err = 0.0;
+    for (int64_t k = 0; k < M; ++k) {
+      double Y[3];
+      for (int al = 0; al < 3; ++al) {
+        const double Q = x[3 * (k + 1) + al] - x[3 * k + al];
+        double kQ = 0.0;
+        for (int be = 0; be < 3; ++be)
+          kQ += p->kappa[3 * al + be] * (x[3 * (k + 1) + be] - x[3 * k + be]);
+        Y[al] = Q + dt * (kQ + v[3 * (k + 1) + al] - v[3 * k + al] + 2.0 * F[3 * k + al]) +
+                (y[3 * (k + 1) + al] - y[3 * k + al]);
+      }
+      const double ylen = sqrt(dot3(Y, Y));
+      const double qlen = (ylen + 2.0 * dt * K * b) / (1.0 + 2.0 * dt * K);
+      for (int al = 0; al < 3; ++al) Qn[3 * k + al] = Y[al] * (qlen / ylen);
+      const double e = fabs(qlen / b - 1.0);
+      if (e > err) err = e;
+    }
+    /* bead 0 by its explicit equation of motion, the rest along the links */
+    double x0[3];
+    for (int al = 0; al < 3; ++al) {
+      const double kx = p->kappa[3 * al] * x[0] + p->kappa[3 * al + 1] * x[1] +
+                        p->kappa[3 * al + 2] * x[2];
+      x0[al] = x[al] + dt * (kx + v[al]) + y[al];
+    }
+    for (int al = 0; al < 3; ++al) x[al] = x0[al];
+    for (int64_t k = 0; k < M; ++k)
+      for (int al = 0; al < 3; ++al) x[3 * (k + 1) + al] = x[3 * k + al] + Qn[3 * k + al];
+    loc.max_rod_err = err;
+  }
+  free(D); free(y); free(F); free(f); free(v); free(Qn);
   if (info) *info = loc;
   return loc.status;
 }

@@ -99,6 +99,18 @@ int bdo_constrain_dense(const bdo_params* p, const double* x_old, double* x_pred
 /* One full timestep: assemble, factor, noise, predictor, constraint. */
 int bdo_step(const bdo_params* p, int64_t step, double* x_inout, bdo_info* info);
 
+/* One timestep with the paper's own stiff Fraenkel springs (Eq. 3) in
+ * place of rigid rods: the semi-implicit link update of Eqs. 13-17.
+ * Spring k (k = 0..N-2) acts on bead k with F_k = K (|Q_k| - b) Q_k/|Q_k|
+ * and on bead k+1 with -F_k; f = the net bead forces at t.  With v = D f,
+ *   Y_k = Q_k + dt [kappa.Q_k + v_{k+1} - v_k + 2 F_k] + y_{k+1} - y_k  (Eq. 14)
+ *   |Q_k'| = (|Y_k| + 2 dt K b) / (1 + 2 dt K),  Q_k' = Y_k |Q_k'|/|Y_k|  (Eqs. 15-17)
+ * and the positions: bead 0 by its explicit equation of motion,
+ * x_0' = x_0 + dt (kappa.x_0 + v_0) + y_0, then x_{k+1}' = x_k' + Q_k'.
+ * info->max_rod_err receives max_k | |Q_k'|/b - 1 |.  k_spring > 0. */
+int bdo_step_fraenkel(const bdo_params* p, double k_spring, int64_t step, double* x_inout,
+                      bdo_info* info);
+
 /* nsteps consecutive steps (step0, step0+1, ...) of one chain. */
 int bdo_run(const bdo_params* p, int64_t step0, int64_t nsteps, double* x_inout, bdo_info* info);
 

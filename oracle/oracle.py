@@ -97,6 +97,8 @@ def lib():
             f.restype = C.c_int
         L.bdo_step.argtypes = [pp, C.c_int64, dp, ip]
         L.bdo_step.restype = C.c_int
+        L.bdo_step_fraenkel.argtypes = [pp, C.c_double, C.c_int64, dp, ip]
+        L.bdo_step_fraenkel.restype = C.c_int
         L.bdo_run.argtypes = [pp, C.c_int64, C.c_int64, dp, ip]
         L.bdo_run.restype = C.c_int
         L.bdo_run_many.argtypes = [pp, C.c_int32, u64p, C.c_int64, C.c_int64, dp,
@@ -196,6 +198,15 @@ def step(p: Params, s: int, x: np.ndarray):
     xx = np.array(x, dtype=np.float64, order="C", copy=True)
     info = Info()
     lib().bdo_step(C.byref(p), s, _dp(xx), C.byref(info))
+    return xx, info.as_dict()
+
+
+def step_fraenkel(p: Params, k_spring: float, s: int, x: np.ndarray):
+    """One step with stiff Fraenkel springs of stiffness k_spring (Eqs. 3,
+    13-17); returns (x', info)."""
+    xx = np.array(x, dtype=np.float64, order="C", copy=True)
+    info = Info()
+    lib().bdo_step_fraenkel(C.byref(p), float(k_spring), s, _dp(xx), C.byref(info))
     return xx, info.as_dict()
 
 
