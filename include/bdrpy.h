@@ -157,6 +157,22 @@ bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_
 bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d_x_inout,
                     bd_precision_t prec, void* d_ws, size_t ws_bytes);
 
+/* One timestep with the paper's own stiff Fraenkel springs (Eq. 3) in
+ * place of rigid rods: D, B and y = c_B B xi as in bd_step, then the
+ * semi-implicit link update of Eqs. 13-17.  Spring k pulls bead k with
+ * F_k = K (|Q_k| - b) Q_k/|Q_k| (K = k_spring > 0) and bead k+1 with -F_k;
+ * with v = D f (f the net bead forces at t, matrix-free product)
+ *   Y_k = Q_k + dt [kappa.Q_k + v_{k+1} - v_k + 2 F_k] + y_{k+1} - y_k,
+ *   |Q_k'| = (|Y_k| + 2 dt K b) / (1 + 2 dt K) along Y_k (Eq. 17);
+ * bead 0 moves by its explicit equation of motion,
+ * x_0' = x_0 + dt (kappa.x_0 + v_0) + y_0, and x_{k+1}' = x_k' + Q_k'.
+ * d_x_inout: N x 3 (N <= 4097, BD_ERR_UNSUPPORTED above), advanced in
+ * place; d_ws: bd_workspace_size(BD_OP_STEP, 3N, prec) bytes.  max_rod_err
+ * of bd_get_info receives max_k | |Q_k'|/b - 1 |; the Newton fields are 0.
+ * A non-positive pivot leaves the positions unchanged. */
+bd_status_t bd_step_fraenkel(bd_handle_t h, const bd_params_t* p, double k_spring, int64_t step,
+                             double* d_x_inout, bd_precision_t prec, void* d_ws, size_t ws_bytes);
+
 /* Synchronise the handle's stream and return the info of the last call. */
 bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out);
 

@@ -33,7 +33,7 @@ EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_
            "bd_cholesky", "bd_brownian", "bd_constrain", "bd_step", "bd_get_info",
            "bd_profile_begin", "bd_profile_end", "bd_ensemble_workspace_size",
            "bd_ensemble_create", "bd_ensemble_step", "bd_ensemble_get_info",
-           "bd_ensemble_destroy")
+           "bd_ensemble_destroy", "bd_step_fraenkel")
 
 
 class BdError(RuntimeError):
@@ -127,6 +127,7 @@ def lib():
         L.bd_ensemble_step.argtypes = [vp, C.c_int64]
         L.bd_ensemble_get_info.argtypes = [vp, C.POINTER(Info)]
         L.bd_ensemble_destroy.argtypes = [vp]
+        L.bd_step_fraenkel.argtypes = [vp, pp, C.c_double, C.c_int64, dp, C.c_int, vp, C.c_size_t]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -240,6 +241,15 @@ class Handle:
         self._sync_stream()
         _check(lib().bd_step(self._h, C.byref(p), step, _dev_f64(x, "x", n), prec, ws.data_ptr(),
                              ws.numel() * ws.element_size()), "bd_step")
+
+    def step_fraenkel(self, p: Params, k_spring: float, step: int, x: torch.Tensor,
+                      prec: int = PREC_FP64, ws: torch.Tensor | None = None):
+        n = 3 * p.n_beads
+        ws = self.workspace(OP_STEP, n, prec) if ws is None else ws
+        self._sync_stream()
+        _check(lib().bd_step_fraenkel(self._h, C.byref(p), float(k_spring), step,
+                                      _dev_f64(x, "x", n), prec, ws.data_ptr(),
+                                      ws.numel() * ws.element_size()), "bd_step_fraenkel")
 
     def profile_begin(self):
         self._sync_stream()

@@ -14,6 +14,7 @@
 
 namespace bd {
 int constrain_max_beads();
+int fraenkel_max_beads();
 Profiler* profiler_new();
 void profiler_delete(Profiler* p);
 int profiler_collect(Profiler* p, hipStream_t s, bd_kernel_stat_t* out, int max_out);
@@ -351,6 +352,38 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
                        s, d_x, xs, n, h->st);
     he = hipGetLastError();
   }
+  return hip_status(he);
+}
+
+bd_status_t bd_step_fraenkel(bd_handle_t h, const bd_params_t* p, double k_spring, int64_t step,
+                             double* d_x, bd_precision_t prec, void* d_ws, size_t ws_bytes) {
+  CallScope scope(h);
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!params_ok(p) || !d_x || !d_ws || !prec_ok(prec)) return BD_ERR_PARAM;
+  if (!(k_spring > 0.0) || !isfinite(k_spring)) return BD_ERR_PARAM;
+  if (p->n_beads > bd::fraenkel_max_beads()) return BD_ERR_UNSUPPORTED;
+  const int64_t n = 3 * (int64_t)p->n_beads;
+  const StepLayout L = step_layout(n, prec);
+  if (ws_bytes < L.total) return BD_ERR_PARAM;
+  char* base = static_cast<char*>(d_ws);
+  double* D = reinterpret_cast<double*>(base + L.d);
+  double* y = reinterpret_cast<double*>(base + L.y);
+  // bead forces and D f in the tension solve's region
+  double* f = reinterpret_cast<double*>(base + L.cons);
+  double* v = reinterpret_cast<double*>(base + L.cons + bd::align_up(sizeof(double) * n, 256));
+  const int64_t ld = step_ld(n);
+  hipStream_t s = h->stream;
+  hipError_t he = reset(h);
+  if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
+  if (he == hipSuccess)
+    he = bd::launch_cholesky(s, h->aux, h->ev, n, D, ld, prec, base + L.chol, h->st,
+                              h->step_panels, h->wide_rows, h->tile_potrf);
+  if (he == hipSuccess)
+    he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
+  if (he == hipSuccess) he = bd::launch_spring_forces(s, d_x, p->n_beads, k_spring, p->b, f);
+  if (he == hipSuccess) he = bd::launch_dmatvec(s, *p, d_x, f, v, h->st);
+  if (he == hipSuccess) he = bd::launch_fraenkel_update(s, *p, k_spring, d_x, v, y, h->st);
   return hip_status(he);
 }
 

@@ -58,6 +58,17 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
                             double* T_out, void* ws, DevState* st, DevState* host_state_pinned,
                             int* pairs_hint);
 
+// r = D(x) f, matrix-free (the tension solve's product); st->done must be 0.
+hipError_t launch_dmatvec(hipStream_t s, const bd_params_t& p, const double* x, const double* f,
+                          double* r, const DevState* st);
+
+// fraenkel.hip
+int fraenkel_max_beads();
+hipError_t launch_spring_forces(hipStream_t s, const double* x, int N, double K, double b,
+                                double* f);
+hipError_t launch_fraenkel_update(hipStream_t s, const bd_params_t& p, double K, double* x,
+                                  const double* v, const double* y, DevState* st);
+
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // ---------------------------------------------------------------- ensembles

@@ -892,6 +892,14 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
 
 int constrain_mv_blocks(int n_beads) { return (n_beads + kMvI - 1) / kMvI; }
 
+hipError_t launch_dmatvec(hipStream_t s, const bd_params_t& p, const double* x, const double* f,
+                          double* r, const DevState* st) {
+  const int N = p.n_beads;
+  BD_LAUNCH("dmatvec", dmatvec_kernel, dim3((N + kMvI - 1) / kMvI), dim3(kMvThreads), 0, s, x, f,
+            r, N, rpy_const(p.hstar, p.a), st);
+  return hipGetLastError();
+}
+
 hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads,
                                     const int32_t* mv_prefix, int mv_blocks, int newton_maxit,
                                     DevState* st, DevState* host_states, int* pairs_hint) {
