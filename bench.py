@@ -231,6 +231,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=20,
                     help="timed steps of the 256-chain ensemble leg (0: skip it)")
+    ap.add_argument("--fraenkel-steps", type=int, default=50,
+                    help="timed steps of the stiff-spring leg at N = 4096 (0: skip it)")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="run only the ensemble leg and print its record")
     ap.add_argument("--only", choices=["all", "mixed", "fp64"], default="all",
@@ -452,6 +454,32 @@ def main() -> int:
 
     ens = ensemble_leg(B, I, torch, np, precs, args, dev) if args.ensemble_steps > 0 else None
 
+    # ------------------------------- stiff Fraenkel springs (Eqs. 13-17)
+    fraenkel = None
+    if args.fraenkel_steps > 0:
+        K = 1e4
+        fraenkel = {"k_spring": K, "workload": w.name}
+        for name, prec in precs.items():
+            ws = h.workspace(B.OP_STEP, n, prec)
+            xx = x0.clone()
+            for s in range(3):
+                h.step_fraenkel(p, K, s, xx, prec, ws)
+            if h.info()["status"] != B.OK:
+                raise RuntimeError(f"fraenkel {name} warmup failed")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(args.fraenkel_steps):
+                h.step_fraenkel(p, K, 3 + s, xx, prec, ws)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = h.info()
+            if st["status"] != B.OK:
+                raise RuntimeError(f"fraenkel {name} timed steps failed")
+            fraenkel[name] = {"steps_per_s": args.fraenkel_steps / wall,
+                              "ms_per_step": 1e3 * wall / args.fraenkel_steps,
+                              "max_spring_extension_last": st["max_rod_err"]}
+            log(f"fraenkel {name}: {fraenkel[name]['steps_per_s']:.2f} steps/s")
+
     mixed = result.get("mixed")
     fp64 = result.get("fp64")
     headrec = result[head]
@@ -479,6 +507,7 @@ def main() -> int:
         "other_precision_profile": other,
         "cpu_baseline": cpu,
         "ensemble": ens,
+        "fraenkel": fraenkel,
         "context": extra,
     }
     print(json.dumps(out), flush=True)
