@@ -4,10 +4,9 @@
   direction u diffuses on the sphere with D_r = 2 (1 - A_perp) / b^2, where
   A_perp is the transverse RPY coefficient of Eq. 8 at R = b, so
   <u(t).u(0)> = exp(-2 D_r t).
-* Freely-jointed equilibrium with HI off: <R_ee^2> = (N-1) b^2 (the
-  equilibrium check the benchmark spec asks for; Section 5 validates the
-  code against the equilibrium scaling R_ee ~ N^0.5).  Started from a straight
-  chain so that the test does not pass trivially.
+* Freely-jointed equilibrium with HI off: <R_ee^2> = (N-1) b^2 (Section 5
+  validates the code against the equilibrium scaling R_ee ~ N^0.5).
+  Started from a straight chain so that the test does not pass trivially.
 """
 import numpy as np
 import pytest
