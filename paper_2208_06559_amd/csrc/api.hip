@@ -159,8 +159,10 @@ struct bd_ensemble_s {
   DevState* host_st;                 // pinned mirror
   int pairs_hint;
   int step_panels;                   // Cholesky panels per step (2 or 4)
-  int32_t* mv_prefix;                // device: flattened matrix-free product grid
-  int mv_blocks;
+  int32_t* mv_prefix;                // device: flattened grids (matrix-free product,
+  int32_t* rpy_prefix;               // assembly, noise product tiles)
+  int32_t* trmv_prefix;
+  int mv_blocks, rpy_blocks, trmv_blocks;
   bd::BatchTables tb;                // flattened grids of the factorisation
   int32_t* tb_dev;                   // device copy of tb.host
 };
@@ -446,6 +448,8 @@ bd_status_t bd_ensemble_workspace_size(int32_t n_chains, const bd_params_t* p,
 static void ensemble_release(bd_ensemble_s* e) {
   if (e->cd) (void)hipFree(e->cd);
   if (e->mv_prefix) (void)hipFree(e->mv_prefix);
+  if (e->rpy_prefix) (void)hipFree(e->rpy_prefix);
+  if (e->trmv_prefix) (void)hipFree(e->trmv_prefix);
   if (e->tb_dev) (void)hipFree(e->tb_dev);
   if (e->st) (void)hipFree(e->st);
   if (e->host_st) (void)hipHostFree(e->host_st);
@@ -475,8 +479,8 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
   e->st = nullptr;
   e->host_st = nullptr;
   e->pairs_hint = 0;
-  e->mv_prefix = nullptr;
-  e->mv_blocks = 0;
+  e->mv_prefix = e->rpy_prefix = e->trmv_prefix = nullptr;
+  e->mv_blocks = e->rpy_blocks = e->trmv_blocks = 0;
   e->tb_dev = nullptr;
   // BDRPY_ENS_PANELS=2 takes two-panel factorisation steps (for
   // comparisons); by default four: with many chains sharing each launch the
@@ -487,7 +491,9 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
       hipMalloc(&e->st, sizeof(DevState) * (size_t)n_chains) != hipSuccess ||
       hipHostMalloc(&e->host_st, sizeof(DevState) * (size_t)n_chains, hipHostMallocDefault) !=
           hipSuccess ||
-      hipMalloc(&e->mv_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess) {
+      hipMalloc(&e->mv_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess ||
+      hipMalloc(&e->rpy_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess ||
+      hipMalloc(&e->trmv_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess) {
     ensemble_release(e);
     return BD_ERR_ALLOC;
   }
@@ -544,10 +550,24 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
   std::stable_sort(e->host.begin(), e->host.end(),
                    [](const bd::ChainDesc& a, const bd::ChainDesc& b) { return a.n > b.n; });
   memset(e->host_st, 0, sizeof(DevState) * (size_t)n_chains);
-  std::vector<int32_t> prefix((size_t)n_chains + 1, 0);
-  for (int32_t c = 0; c < n_chains; ++c)
-    prefix[(size_t)c + 1] = prefix[(size_t)c] + bd::constrain_mv_blocks(e->host[(size_t)c].N);
+  std::vector<int32_t> prefix((size_t)n_chains + 1, 0), rpre(prefix), tpre(prefix);
+  int64_t pm = 0, pr = 0, pt = 0;  // grids must stay within int32
+  for (int32_t c = 0; c < n_chains; ++c) {
+    const bd::ChainDesc& d = e->host[(size_t)c];
+    pm += bd::constrain_mv_blocks(d.N);
+    pr += bd::rpy_batched_blocks(d.N);
+    pt += bd::trmv_batched_blocks(d.n);
+    if (pm > INT32_MAX || pr > INT32_MAX || pt > INT32_MAX) {
+      ensemble_release(e);
+      return BD_ERR_UNSUPPORTED;
+    }
+    prefix[(size_t)c + 1] = (int32_t)pm;
+    rpre[(size_t)c + 1] = (int32_t)pr;
+    tpre[(size_t)c + 1] = (int32_t)pt;
+  }
   e->mv_blocks = prefix[(size_t)n_chains];
+  e->rpy_blocks = rpre[(size_t)n_chains];
+  e->trmv_blocks = tpre[(size_t)n_chains];
   // record the factorisation's flattened grids (no launches), then upload
   e->tb.record = true;
   hipError_t rec = hipSuccess;
@@ -568,6 +588,10 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
   if (hipMemcpy(e->cd, e->host.data(), sizeof(bd::ChainDesc) * (size_t)n_chains,
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(e->mv_prefix, prefix.data(), sizeof(int32_t) * prefix.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(e->rpy_prefix, rpre.data(), sizeof(int32_t) * rpre.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(e->trmv_prefix, tpre.data(), sizeof(int32_t) * tpre.size(),
                 hipMemcpyHostToDevice) != hipSuccess ||
       (!e->tb.host.empty() &&
        hipMemcpy(e->tb_dev, e->tb.host.data(), sizeof(int32_t) * e->tb.host.size(),
@@ -593,11 +617,13 @@ bd_status_t bd_ensemble_step(bd_ensemble_t e, int64_t step) {
   BD_LAUNCH("reset_states", reset_states_kernel, dim3((unsigned)((z + 255) / 256)), dim3(256), 0,
             s, e->st, z);
   hipError_t he = hipGetLastError();
-  if (he == hipSuccess) he = bd::launch_rpy_assemble_batched(s, e->cd, z, e->max_beads);
+  if (he == hipSuccess)
+    he = bd::launch_rpy_assemble_batched(s, e->cd, z, e->rpy_prefix, e->rpy_blocks);
   if (he == hipSuccess)
     he = bd::launch_cholesky_batched(s, h->aux, h->ev, e->cd, e->host.data(), z, e->prec,
                                      e->step_panels, &e->tb);
-  if (he == hipSuccess) he = bd::launch_brownian_batched(s, e->cd, z, max_n, step);
+  if (he == hipSuccess)
+    he = bd::launch_brownian_batched(s, e->cd, z, max_n, step, e->trmv_prefix, e->trmv_blocks);
   if (he == hipSuccess) he = bd::launch_predictor_batched(s, e->cd, z, e->max_beads);
   if (he == hipSuccess)
     he = bd::launch_constrain_batched(s, e->cd, z, e->max_beads, e->mv_prefix, e->mv_blocks,

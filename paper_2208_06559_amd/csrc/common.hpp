@@ -129,9 +129,14 @@ struct BatchTables {
 hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev[4],
                                    const ChainDesc* cd, const ChainDesc* cd_host, int count,
                                    bd_precision_t prec, int panels, BatchTables* tb);
-hipError_t launch_rpy_assemble_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads);
+// Flattened grids of the assembly and the noise product: workgroups per
+// chain, and the launchers taking the prefix arrays over the table.
+int rpy_batched_blocks(int n_beads);
+int trmv_batched_blocks(int64_t n);
+hipError_t launch_rpy_assemble_batched(hipStream_t s, const ChainDesc* cd, int count,
+                                       const int32_t* prefix, int blocks);
 hipError_t launch_brownian_batched(hipStream_t s, const ChainDesc* cd, int count, int64_t max_n,
-                                   int64_t step);
+                                   int64_t step, const int32_t* tile_prefix, int tile_blocks);
 hipError_t launch_predictor_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads);
 // Runs the tension solve of every chain; returns once every chain's
 // iteration has finished (polls the `count` states at `st`, which are

@@ -60,13 +60,16 @@ __global__ __launch_bounds__(kRpyThreads) void rpy_assemble_kernel(
   rpy_assemble_body(blockIdx.x, blockIdx.y, x, D, ld, N, hstar, a, fill_full);
 }
 
-// Ensembles: chain blockIdx.z, lower triangle; the grid covers the largest chain.
+// Ensembles: lower triangles, one flattened grid; chain c owns
+// rpy_batched_blocks(N_c) workgroups, (column bead j, row block bx) each.
 __global__ __launch_bounds__(kRpyThreads) void rpy_assemble_batched_kernel(
-    const ChainDesc* __restrict__ cd) {
-  const ChainDesc& c = cd[blockIdx.z];
+    const ChainDesc* __restrict__ cd, const int32_t* __restrict__ prefix, int count) {
+  const int ci = find_chain(prefix, count, blockIdx.x);
+  const ChainDesc& c = cd[ci];
   const int N = c.N;
-  if ((int)blockIdx.y >= N || (int)blockIdx.x * kRpyThreads >= N) return;
-  rpy_assemble_body(blockIdx.x, blockIdx.y, c.x, c.D, c.ld, N, c.hstar, c.a, 0);
+  const int nbx = (N + kRpyThreads - 1) / kRpyThreads;
+  const int local = blockIdx.x - prefix[ci];
+  rpy_assemble_body(local % nbx, local / nbx, c.x, c.D, c.ld, N, c.hstar, c.a, 0);
 }
 
 }  // namespace
@@ -80,10 +83,14 @@ hipError_t launch_rpy_assemble(hipStream_t s, const bd_params_t& p, const double
   return hipGetLastError();
 }
 
+int rpy_batched_blocks(int n_beads) {
+  return n_beads * ((n_beads + kRpyThreads - 1) / kRpyThreads);
+}
+
 hipError_t launch_rpy_assemble_batched(hipStream_t s, const ChainDesc* cd, int count,
-                                       int max_beads) {
-  dim3 grid((max_beads + kRpyThreads - 1) / kRpyThreads, max_beads, count);
-  BD_LAUNCH("rpy_assemble_batched", rpy_assemble_batched_kernel, grid, dim3(kRpyThreads), 0, s, cd);
+                                       const int32_t* prefix, int blocks) {
+  BD_LAUNCH("rpy_assemble_batched", rpy_assemble_batched_kernel, dim3(blocks),
+            dim3(kRpyThreads), 0, s, cd, prefix, count);
   return hipGetLastError();
 }
 
