@@ -219,6 +219,33 @@ def ensemble_leg(B, I, torch, np, precs, args, dev) -> dict:
     return out
 
 
+def fraenkel_leg(B, torch, h, p, x0, n, w, precs, args) -> dict:
+    """bd_step_fraenkel (stiff springs, K = 1e4) on the single-chain workload."""
+    K = 1e4
+    fraenkel = {"k_spring": K, "workload": w.name}
+    for name, prec in precs.items():
+        ws = h.workspace(B.OP_STEP, n, prec)
+        xx = x0.clone()
+        for s in range(3):
+            h.step_fraenkel(p, K, s, xx, prec, ws)
+        if h.info()["status"] != B.OK:
+            raise RuntimeError(f"fraenkel {name} warmup failed")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.fraenkel_steps):
+            h.step_fraenkel(p, K, 3 + s, xx, prec, ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = h.info()
+        if st["status"] != B.OK:
+            raise RuntimeError(f"fraenkel {name} timed steps failed")
+        fraenkel[name] = {"steps_per_s": args.fraenkel_steps / wall,
+                          "ms_per_step": 1e3 * wall / args.fraenkel_steps,
+                          "max_spring_extension_last": st["max_rod_err"]}
+        log(f"fraenkel {name}: {fraenkel[name]['steps_per_s']:.2f} steps/s")
+    return fraenkel
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +260,8 @@ def main() -> int:
                     help="timed steps of the 256-chain ensemble leg (0: skip it)")
     ap.add_argument("--fraenkel-steps", type=int, default=50,
                     help="timed steps of the stiff-spring leg at N = 4096 (0: skip it)")
+    ap.add_argument("--fraenkel-only", action="store_true",
+                    help="run only the stiff-spring leg and print its record")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="run only the ensemble leg and print its record")
     ap.add_argument("--only", choices=["all", "mixed", "fp64"], default="all",
@@ -270,6 +299,11 @@ def main() -> int:
 
     if args.ensemble_only:
         print(json.dumps({"ensemble": ensemble_leg(B, I, torch, np, precs, args, dev)}), flush=True)
+        h.close()
+        return 0
+    if args.fraenkel_only:
+        print(json.dumps({"fraenkel": fraenkel_leg(B, torch, h, p, x0, n, w, precs, args)}),
+              flush=True)
         h.close()
         return 0
 
@@ -453,32 +487,8 @@ def main() -> int:
         log(f"cpu oracle: {cpu}")
 
     ens = ensemble_leg(B, I, torch, np, precs, args, dev) if args.ensemble_steps > 0 else None
+    fraenkel = fraenkel_leg(B, torch, h, p, x0, n, w, precs, args) if args.fraenkel_steps > 0 else None
 
-    # ------------------------------- stiff Fraenkel springs (Eqs. 13-17)
-    fraenkel = None
-    if args.fraenkel_steps > 0:
-        K = 1e4
-        fraenkel = {"k_spring": K, "workload": w.name}
-        for name, prec in precs.items():
-            ws = h.workspace(B.OP_STEP, n, prec)
-            xx = x0.clone()
-            for s in range(3):
-                h.step_fraenkel(p, K, s, xx, prec, ws)
-            if h.info()["status"] != B.OK:
-                raise RuntimeError(f"fraenkel {name} warmup failed")
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for s in range(args.fraenkel_steps):
-                h.step_fraenkel(p, K, 3 + s, xx, prec, ws)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-            st = h.info()
-            if st["status"] != B.OK:
-                raise RuntimeError(f"fraenkel {name} timed steps failed")
-            fraenkel[name] = {"steps_per_s": args.fraenkel_steps / wall,
-                              "ms_per_step": 1e3 * wall / args.fraenkel_steps,
-                              "max_spring_extension_last": st["max_rod_err"]}
-            log(f"fraenkel {name}: {fraenkel[name]['steps_per_s']:.2f} steps/s")
 
     mixed = result.get("mixed")
     fp64 = result.get("fp64")
