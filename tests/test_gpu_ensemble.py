@@ -116,6 +116,27 @@ def test_ensemble_equals_single_chain_bitwise(h, h_wide, prec, panels):
     ens.close()
 
 
+@pytest.mark.parametrize("prec", [B.PREC_FP64, B.PREC_MIXED])
+def test_ensemble_long_chain_bitwise(h, h_wide, prec):
+    """A chain of more than 1024 beads (the ensemble's matrix-free product
+    then stages its beads j in two LDS rounds where the single-chain kernel
+    uses one; the same summation order) and more than 4096 rows (four-panel
+    steps to the end), beside short chains."""
+    chains = _chains([1500, 40, 700], seed=11)
+    xp = _packed(chains)
+    ens = B.Ensemble(h, [pg for pg, _, _ in chains], xp, prec)
+    singles = [torch.tensor(x, dtype=torch.float64, device=DEV) for _, _, x in chains]
+    for s in range(2):
+        ens.step(s)
+        infos = ens.info()
+        for c, (pg, _, _) in enumerate(chains):
+            h_wide.step(pg, s, singles[c], prec)
+            assert h_wide.info() == infos[c], (s, c)
+    for c, xg in enumerate(_split(xp, chains)):
+        assert torch.equal(xg, singles[c]), (prec, c)
+    ens.close()
+
+
 @pytest.mark.parametrize("prec,tol", [(B.PREC_FP64, 1e-10), (B.PREC_MIXED, 1e-6)])
 def test_ensemble_vs_oracle(h, prec, tol):
     chains = _chains(SIZES, seed=7)
