@@ -216,6 +216,29 @@ def ensemble_leg(B, I, torch, np, precs, args, dev) -> dict:
         del ens, xp
         torch.cuda.empty_cache()
     h.close()
+    if not args.no_cpu:
+        # the oracle on every 8th chain by size (32 chains), scaled to the
+        # whole ensemble by sum n^3 (the factorisation dominates its time)
+        from oracle import oracle as o
+        order = np.argsort(sizes, kind="stable")[::8]
+        t_sample, n3_sample = 0.0, 0.0
+        for c in order:
+            d = spec[int(c)]
+            po = o.make_params(d["n_beads"], dt=w.dt, kappa=d["kappa"], seed=d["seed"],
+                               chain_id=d["chain_id"], hstar=w.hstar, a=w.a, b=w.b)
+            t0 = time.perf_counter()
+            o.step(po, 0, d["x"])
+            t_sample += time.perf_counter() - t0
+            n3_sample += float(3 * d["n_beads"]) ** 3
+        n3_all = float(sum(float(3 * int(v)) ** 3 for v in sizes))
+        est = t_sample * n3_all / n3_sample
+        out["cpu_baseline"] = {"value": 1.0 / est, "unit": "ensemble steps/s",
+                               "chain_steps_per_s": w.chains / est, "cores": o.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"1 oracle FP64 step of {len(order)} chains (every 8th "
+                                         f"by size), {t_sample:.2f} s, scaled by sum n^3 "
+                                         f"({n3_all / n3_sample:.2f}x) to the {w.chains} chains"}
+        log(f"ensemble cpu oracle: {out['cpu_baseline']}")
     return out
 
 
