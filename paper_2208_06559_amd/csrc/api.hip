@@ -456,9 +456,18 @@ static void ensemble_release(bd_ensemble_s* e) {
   delete e;
 }
 
-bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_t* p,
-                               bd_precision_t prec, double* d_x, void* d_ws, size_t ws_bytes,
-                               bd_ensemble_t* out) {
+// Releases a partly built ensemble unless disarmed (every error path, and
+// a host allocation failure thrown from inside).
+struct EnsembleGuard {
+  bd_ensemble_s* e;
+  ~EnsembleGuard() {
+    if (e) ensemble_release(e);
+  }
+};
+
+static bd_status_t ensemble_create_impl(bd_handle_t h, int32_t n_chains, const bd_params_t* p,
+                                        bd_precision_t prec, double* d_x, void* d_ws,
+                                        size_t ws_bytes, bd_ensemble_t* out) {
   if (!out) return BD_ERR_PARAM;
   *out = nullptr;
   bd_status_t err = enter(h);
@@ -470,6 +479,7 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
     return BD_ERR_PARAM;
   bd_ensemble_s* e = new (std::nothrow) bd_ensemble_s;
   if (!e) return BD_ERR_ALLOC;
+  EnsembleGuard guard{e};
   e->h = h;
   e->count = n_chains;
   e->prec = prec;
@@ -494,15 +504,9 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
       hipMalloc(&e->mv_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess ||
       hipMalloc(&e->rpy_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess ||
       hipMalloc(&e->trmv_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess) {
-    ensemble_release(e);
     return BD_ERR_ALLOC;
   }
-  try {
-    e->host.resize((size_t)n_chains);
-  } catch (...) {
-    ensemble_release(e);
-    return BD_ERR_ALLOC;
-  }
+  e->host.resize((size_t)n_chains);
   char* base = static_cast<char*>(d_ws);
   int64_t xoff = 0;
   for (int32_t c = 0; c < n_chains; ++c) {
@@ -558,8 +562,7 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
     pr += bd::rpy_batched_blocks(d.N);
     pt += bd::trmv_batched_blocks(d.n);
     if (pm > INT32_MAX || pr > INT32_MAX || pt > INT32_MAX) {
-      ensemble_release(e);
-      return BD_ERR_UNSUPPORTED;
+        return BD_ERR_UNSUPPORTED;
     }
     prefix[(size_t)c + 1] = (int32_t)pm;
     rpre[(size_t)c + 1] = (int32_t)pr;
@@ -570,18 +573,12 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
   e->trmv_blocks = tpre[(size_t)n_chains];
   // record the factorisation's flattened grids (no launches), then upload
   e->tb.record = true;
-  hipError_t rec = hipSuccess;
-  try {
-    rec = bd::launch_cholesky_batched(h->stream, h->aux, h->ev, e->cd, e->host.data(), n_chains,
-                                      prec, e->step_panels, &e->tb);
-  } catch (...) {
-    ensemble_release(e);
-    return BD_ERR_ALLOC;
-  }
+  const hipError_t rec = bd::launch_cholesky_batched(h->stream, h->aux, h->ev, e->cd,
+                                                     e->host.data(), n_chains, prec,
+                                                     e->step_panels, &e->tb);
   e->tb.record = false;
   if (rec != hipSuccess ||
       hipMalloc(&e->tb_dev, sizeof(int32_t) * (e->tb.host.size() + 1)) != hipSuccess) {
-    ensemble_release(e);
     return rec != hipSuccess ? BD_ERR_PARAM : BD_ERR_ALLOC;
   }
   e->tb.dev = e->tb_dev;
@@ -598,11 +595,22 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
                  hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemcpy(e->st, e->host_st, sizeof(DevState) * (size_t)n_chains, hipMemcpyHostToDevice) !=
           hipSuccess) {
-    ensemble_release(e);
     return BD_ERR_HIP;
   }
+  guard.e = nullptr;
   *out = e;
   return BD_OK;
+}
+
+bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_t* p,
+                               bd_precision_t prec, double* d_x, void* d_ws, size_t ws_bytes,
+                               bd_ensemble_t* out) {
+  try {
+    return ensemble_create_impl(h, n_chains, p, prec, d_x, d_ws, ws_bytes, out);
+  } catch (...) {  // a host allocation failed: no exception crosses the C ABI
+    if (out) *out = nullptr;
+    return BD_ERR_ALLOC;
+  }
 }
 
 bd_status_t bd_ensemble_step(bd_ensemble_t e, int64_t step) {
