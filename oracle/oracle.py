@@ -210,6 +210,18 @@ def step_fraenkel(p: Params, k_spring: float, s: int, x: np.ndarray):
     return xx, info.as_dict()
 
 
+def observables(x: np.ndarray) -> np.ndarray:
+    """Chain observables of the flow studies (Section 5) for one chain x
+    (N x 3): the end-to-end vector R_ee = r_{N-1} - r_0 and the squared
+    radius of gyration R_g^2 = (1/N) sum_i |r_i - r_cm|^2, as
+    [R_ee,x, R_ee,y, R_ee,z, R_g^2]."""
+    x = np.asarray(x, dtype=np.float64)
+    ree = x[-1] - x[0]
+    rcm = x.mean(axis=0)
+    rg2 = np.sum((x - rcm) ** 2) / len(x)
+    return np.concatenate([ree, [rg2]])
+
+
 def run(p: Params, step0: int, nsteps: int, x: np.ndarray):
     xx = np.array(x, dtype=np.float64, order="C", copy=True)
     info = Info()
