@@ -173,6 +173,17 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
 bd_status_t bd_step_fraenkel(bd_handle_t h, const bd_params_t* p, double k_spring, int64_t step,
                              double* d_x_inout, bd_precision_t prec, void* d_ws, size_t ws_bytes);
 
+/* Observables of the paper's flow studies (Section 5) for n_chains chains
+ * packed in d_x: chain c is beads d_offsets[c] .. d_offsets[c+1]-1 (rows of
+ * d_x, N x 3 each; d_offsets: device, n_chains + 1 increasing values, every
+ * chain at least one bead; the call does not check them).  d_out (device,
+ * 4 n_chains doubles) receives per chain the end-to-end vector
+ * R_ee = r_{N-1} - r_0 (three components: stretch |R_ee| / ((N-1) b),
+ * R_ee,y, ...) and R_g^2 = (1/N) sum_i |r_i - r_cm|^2.  Asynchronous on
+ * the handle's stream. */
+bd_status_t bd_observables(bd_handle_t h, int32_t n_chains, const double* d_x,
+                           const int64_t* d_offsets, double* d_out);
+
 /* Synchronise the handle's stream and return the info of the last call. */
 bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out);
 

@@ -33,7 +33,7 @@ EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_
            "bd_cholesky", "bd_brownian", "bd_constrain", "bd_step", "bd_get_info",
            "bd_profile_begin", "bd_profile_end", "bd_ensemble_workspace_size",
            "bd_ensemble_create", "bd_ensemble_step", "bd_ensemble_get_info",
-           "bd_ensemble_destroy", "bd_step_fraenkel")
+           "bd_ensemble_destroy", "bd_step_fraenkel", "bd_observables")
 
 
 class BdError(RuntimeError):
@@ -128,6 +128,7 @@ def lib():
         L.bd_ensemble_get_info.argtypes = [vp, C.POINTER(Info)]
         L.bd_ensemble_destroy.argtypes = [vp]
         L.bd_step_fraenkel.argtypes = [vp, pp, C.c_double, C.c_int64, dp, C.c_int, vp, C.c_size_t]
+        L.bd_observables.argtypes = [vp, C.c_int32, dp, vp, dp]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -250,6 +251,20 @@ class Handle:
         _check(lib().bd_step_fraenkel(self._h, C.byref(p), float(k_spring), step,
                                       _dev_f64(x, "x", n), prec, ws.data_ptr(),
                                       ws.numel() * ws.element_size()), "bd_step_fraenkel")
+
+    def observables(self, x: torch.Tensor, n_beads) -> torch.Tensor:
+        """(n_chains, 4) tensor: R_ee (3 components) and R_g^2 per chain of
+        the packed positions x (chain c has n_beads[c] beads)."""
+        counts = [int(v) for v in n_beads]
+        if not counts or min(counts) < 1:
+            raise ValueError("n_beads: every chain needs at least one bead")
+        off = torch.tensor([0] + list(np.cumsum(counts)), dtype=torch.int64,
+                           device=f"cuda:{self.device}")
+        out = torch.empty((len(counts), 4), dtype=torch.float64, device=f"cuda:{self.device}")
+        self._sync_stream()
+        _check(lib().bd_observables(self._h, len(counts), _dev_f64(x, "x", 3 * sum(counts)),
+                                    off.data_ptr(), out.data_ptr()), "bd_observables")
+        return out
 
     def profile_begin(self):
         self._sync_stream()

@@ -389,6 +389,15 @@ bd_status_t bd_step_fraenkel(bd_handle_t h, const bd_params_t* p, double k_sprin
   return hip_status(he);
 }
 
+bd_status_t bd_observables(bd_handle_t h, int32_t n_chains, const double* d_x,
+                           const int64_t* d_offsets, double* d_out) {
+  CallScope scope(h);
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (n_chains < 1 || n_chains > 2147483647 || !d_x || !d_offsets || !d_out) return BD_ERR_PARAM;
+  return hip_status(bd::launch_observables(h->stream, n_chains, d_x, d_offsets, d_out));
+}
+
 bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out) {
   bd_status_t e = enter(h);
   if (e != BD_OK) return e;

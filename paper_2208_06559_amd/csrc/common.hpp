@@ -62,6 +62,10 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
 hipError_t launch_dmatvec(hipStream_t s, const bd_params_t& p, const double* x, const double* f,
                           double* r, const DevState* st);
 
+// observables.hip
+hipError_t launch_observables(hipStream_t s, int32_t n_chains, const double* x,
+                              const int64_t* off, double* out);
+
 // fraenkel.hip
 int fraenkel_max_beads();
 hipError_t launch_spring_forces(hipStream_t s, const double* x, int N, double K, double b,
