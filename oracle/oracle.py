@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
 the CPU-baseline leg of ``bench.py`` may import this module.  It shares no
 code with the HIP library or its Python binding.
 
-Every function mirrors one routine of ``oracle/bdo.c``; the equations each
-follows are cited there (arXiv 2208.06559, Sections 3-4).
+Every function mirrors one routine of ``oracle/bdo.c``, where the equations
+each follows are cited (arXiv 2208.06559, Sections 3-4), except
+``observables``, which is written here in numpy from its definition.
 """
 from __future__ import annotations
 
