@@ -137,6 +137,23 @@ def test_ensemble_long_chain_bitwise(h, h_wide, prec):
     ens.close()
 
 
+@pytest.mark.parametrize("sizes", [[300], [50, 50, 50, 50], [2, 2]])
+def test_ensemble_edge_shapes_bitwise(h, h_wide, sizes):
+    """One chain; equal sizes (ties in the size order); only two-bead
+    chains (less than one panel)."""
+    chains = _chains(sizes, seed=13)
+    xp = _packed(chains)
+    ens = B.Ensemble(h, [pg for pg, _, _ in chains], xp, B.PREC_MIXED)
+    ens.step(4)
+    infos = ens.info()
+    for c, (xg, (pg, _, x0)) in enumerate(zip(_split(xp, chains), chains)):
+        single = torch.tensor(x0, dtype=torch.float64, device=DEV)
+        h_wide.step(pg, 4, single, B.PREC_MIXED)
+        assert h_wide.info() == infos[c], c
+        assert torch.equal(xg, single), c
+    ens.close()
+
+
 @pytest.mark.parametrize("prec,tol", [(B.PREC_FP64, 1e-10), (B.PREC_MIXED, 1e-6)])
 def test_ensemble_vs_oracle(h, prec, tol):
     chains = _chains(SIZES, seed=7)
