@@ -6,7 +6,8 @@ code with the HIP library or its Python binding.
 
 Every function mirrors one routine of ``oracle/bdo.c``, where the equations
 each follows are cited (arXiv 2208.06559, Sections 3-4), except
-``observables``, which is written here in numpy from its definition.
+``observables`` and ``rpy_assemble_adjoint``, which are written here in
+numpy from their definitions.
 """
 from __future__ import annotations
 
@@ -221,6 +222,55 @@ def observables(x: np.ndarray) -> np.ndarray:
     rcm = x.mean(axis=0)
     rg2 = np.sum((x - rcm) ** 2) / len(x)
     return np.concatenate([ree, [rg2]])
+
+
+def _rpy_coeffs_and_slopes(hstar: float, a: float, R: float):
+    """cI, cRR of D_ij = cI I + cRR R R^T (Eqs. 8-9) and their derivatives
+    with respect to R = |r_i - r_j| > 0."""
+    if R >= 2 * a:
+        pre = 0.75 * hstar
+        cI = pre * (1 / R + 2 * a * a / (3 * R ** 3))
+        cRR = pre * (1 / R ** 3 - 2 * a * a / R ** 5)
+        dcI = pre * (-1 / R ** 2 - 2 * a * a / R ** 4)
+        dcRR = pre * (-3 / R ** 4 + 10 * a * a / R ** 6)
+    else:
+        pre = 3 * hstar / (8 * a)
+        cI = pre * (8 / 3 - 3 * R / (4 * a))
+        cRR = pre / (4 * a * R)
+        dcI = -pre * 3 / (4 * a)
+        dcRR = -pre / (4 * a * R * R)
+    return cI, cRR, dcI, dcRR
+
+
+def rpy_assemble_adjoint(p: Params, x: np.ndarray, Dbar: np.ndarray):
+    """Adjoint of the assembly (Eqs. 7-9): for phi = sum_ij <Dbar_ij, D_ij>
+    (3 x 3 blocks, Dbar a full n x n matrix), returns (d phi/d x (N x 3),
+    d phi/d h*).  With R = r_i - r_j, R = |R|, Rh = R/R and B = Dbar_ij,
+    <B, D_ij> = cI tr B + cRR R^T B R, so its gradient in R is
+    cI' tr(B) Rh + cRR' (R^T B R) Rh + cRR (B + B^T) R, added to bead i and
+    subtracted from bead j; D - I is linear in h*.  Coincident beads are
+    rejected (the near-field block is not differentiable at R = 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    N = len(x)
+    xbar = np.zeros((N, 3))
+    hbar = 0.0
+    for i in range(N):
+        for j in range(N):
+            if i == j:
+                continue
+            Rv = x[i] - x[j]
+            R = float(np.sqrt(Rv @ Rv))
+            if R == 0.0:
+                raise ValueError("coincident beads")
+            B = Dbar[3 * i:3 * i + 3, 3 * j:3 * j + 3]
+            cI, cRR, dcI, dcRR = _rpy_coeffs_and_slopes(p.hstar, p.a, R)
+            q = Rv @ B @ Rv
+            g = dcI * np.trace(B) * Rv / R + dcRR * q * Rv / R + cRR * (B + B.T) @ Rv
+            xbar[i] += g
+            xbar[j] -= g
+            uI, uRR, _, _ = _rpy_coeffs_and_slopes(1.0, p.a, R)  # per unit h*
+            hbar += uI * np.trace(B) + uRR * q
+    return xbar, hbar
 
 
 def run(p: Params, step0: int, nsteps: int, x: np.ndarray):
