@@ -123,6 +123,17 @@ bd_status_t bd_workspace_size(bd_op_t op, int64_t n, bd_precision_t prec, size_t
 bd_status_t bd_rpy_assemble(bd_handle_t h, const bd_params_t* p, const double* d_x, double* d_D,
                             int64_t ld, bd_fill_t fill);
 
+/* Adjoint of the assembly (Eqs. 7-9), the first step of differentiating
+ * the path: for phi = sum_ij <Dbar_ij, D_ij(x)> with Dbar a full n x n
+ * matrix (d_Dbar, column-major, ld >= n, both triangles read), writes
+ * d phi/d x to d_xbar (N x 3) and d phi/d h* to d_hbar (one double).
+ * d_ws: at least 8 N bytes.  Coincident beads (where the near-field block
+ * is not differentiable) set status BD_ERR_PARAM in bd_get_info; the
+ * outputs are then unspecified. */
+bd_status_t bd_rpy_assemble_adjoint(bd_handle_t h, const bd_params_t* p, const double* d_x,
+                                    const double* d_Dbar, int64_t ld, double* d_xbar,
+                                    double* d_hbar, void* d_ws, size_t ws_bytes);
+
 /* In-place Cholesky D = B B^T (Eq. 10) of the lower triangle of d_A
  * (n x n column-major, ld >= n); B overwrites the lower triangle, the strict
  * upper triangle is not touched.  Blocked right-looking: FP64 diagonal

@@ -33,7 +33,8 @@ EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_
            "bd_cholesky", "bd_brownian", "bd_constrain", "bd_step", "bd_get_info",
            "bd_profile_begin", "bd_profile_end", "bd_ensemble_workspace_size",
            "bd_ensemble_create", "bd_ensemble_step", "bd_ensemble_get_info",
-           "bd_ensemble_destroy", "bd_step_fraenkel", "bd_observables")
+           "bd_ensemble_destroy", "bd_step_fraenkel", "bd_observables",
+           "bd_rpy_assemble_adjoint")
 
 
 class BdError(RuntimeError):
@@ -129,6 +130,7 @@ def lib():
         L.bd_ensemble_destroy.argtypes = [vp]
         L.bd_step_fraenkel.argtypes = [vp, pp, C.c_double, C.c_int64, dp, C.c_int, vp, C.c_size_t]
         L.bd_observables.argtypes = [vp, C.c_int32, dp, vp, dp]
+        L.bd_rpy_assemble_adjoint.argtypes = [vp, pp, dp, dp, C.c_int64, dp, dp, vp, C.c_size_t]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -251,6 +253,21 @@ class Handle:
         _check(lib().bd_step_fraenkel(self._h, C.byref(p), float(k_spring), step,
                                       _dev_f64(x, "x", n), prec, ws.data_ptr(),
                                       ws.numel() * ws.element_size()), "bd_step_fraenkel")
+
+    def rpy_assemble_adjoint(self, p: Params, x: torch.Tensor, Dbar: torch.Tensor, ld: int):
+        """(d phi/d x (N x 3), d phi/d h* (1-element tensor)) for
+        phi = <Dbar, D(x)>, Dbar a column-major (n, ld) buffer."""
+        n = 3 * p.n_beads
+        dev = f"cuda:{self.device}"
+        xbar = torch.empty((p.n_beads, 3), dtype=torch.float64, device=dev)
+        hbar = torch.empty(1, dtype=torch.float64, device=dev)
+        ws = torch.empty(max(p.n_beads, 1), dtype=torch.float64, device=dev)
+        self._sync_stream()
+        _check(lib().bd_rpy_assemble_adjoint(self._h, C.byref(p), _dev_f64(x, "x", n),
+                                             _dev_f64(Dbar, "Dbar", (n - 1) * ld + n), ld,
+                                             xbar.data_ptr(), hbar.data_ptr(), ws.data_ptr(),
+                                             ws.numel() * 8), "bd_rpy_assemble_adjoint")
+        return xbar, hbar
 
     def observables(self, x: torch.Tensor, n_beads) -> torch.Tensor:
         """(n_chains, 4) tensor: R_ee (3 components) and R_g^2 per chain of

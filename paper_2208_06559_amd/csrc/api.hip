@@ -389,6 +389,20 @@ bd_status_t bd_step_fraenkel(bd_handle_t h, const bd_params_t* p, double k_sprin
   return hip_status(he);
 }
 
+bd_status_t bd_rpy_assemble_adjoint(bd_handle_t h, const bd_params_t* p, const double* d_x,
+                                    const double* d_Dbar, int64_t ld, double* d_xbar,
+                                    double* d_hbar, void* d_ws, size_t ws_bytes) {
+  CallScope scope(h);
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!params_ok(p) || !d_x || !d_Dbar || !d_xbar || !d_hbar || !d_ws) return BD_ERR_PARAM;
+  const int64_t n = 3 * (int64_t)p->n_beads;
+  if (ld < n || ws_bytes < sizeof(double) * (size_t)p->n_beads) return BD_ERR_PARAM;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
+  return hip_status(bd::launch_rpy_adjoint(h->stream, *p, d_x, d_Dbar, ld, d_xbar, d_hbar,
+                                           static_cast<double*>(d_ws), h->st));
+}
+
 bd_status_t bd_observables(bd_handle_t h, int32_t n_chains, const double* d_x,
                            const int64_t* d_offsets, double* d_out) {
   CallScope scope(h);

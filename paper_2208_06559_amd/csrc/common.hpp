@@ -39,6 +39,10 @@ constexpr int kMaxStep = 4 * kNB;  // widest factorisation step (four panels)
 hipError_t launch_rpy_assemble(hipStream_t s, const bd_params_t& p, const double* x, double* D,
                                int64_t ld, int fill);
 
+hipError_t launch_rpy_adjoint(hipStream_t s, const bd_params_t& p, const double* x,
+                              const double* Dbar, int64_t ld, double* xbar, double* hbar,
+                              double* hpart, DevState* st);
+
 // cholesky.hip
 size_t cholesky_workspace_bytes(int64_t n, bd_precision_t prec);
 hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int64_t n, double* A,

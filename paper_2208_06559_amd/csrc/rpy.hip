@@ -72,7 +72,115 @@ __global__ __launch_bounds__(kRpyThreads) void rpy_assemble_batched_kernel(
   rpy_assemble_body(local % nbx, local / nbx, c.x, c.D, c.ld, N, c.hstar, c.a, 0);
 }
 
+// Adjoint of the assembly: for phi = sum_ij <Dbar_ij, D_ij> (3 x 3 blocks of
+// the full n x n matrix Dbar, column-major with ld), bead i receives
+// sum_{j != i} g(Dbar_ij + Dbar_ji, R_ij) with, for R = r_i - r_j and
+// <B, D_ij> = cI tr B + cRR R^T B R,
+//   g(B, R) = cI'(R) tr(B) R/|R| + cRR'(R) (R^T B R) R/|R| + cRR (B + B^T) R,
+// and the h* partial sum_j (cI tr Dbar_ij + cRR R^T Dbar_ij R) / h* (D - I
+// is linear in h*).  One work-item per bead i; j ascending.
+__device__ __forceinline__ void rpy_slopes(double R, double hstar, double a, double& cI,
+                                           double& cRR, double& dcI, double& dcRR) {
+  if (R >= 2.0 * a) {
+    const double pre = 0.75 * hstar, a2 = a * a;
+    cI = pre * (1.0 / R + 2.0 * a2 / (3.0 * R * R * R));
+    cRR = pre * (1.0 / (R * R * R) - 2.0 * a2 / (R * R * R * R * R));
+    dcI = pre * (-1.0 / (R * R) - 2.0 * a2 / (R * R * R * R));
+    dcRR = pre * (-3.0 / (R * R * R * R) + 10.0 * a2 / (R * R * R * R * R * R));
+  } else {
+    const double pre = 3.0 * hstar / (8.0 * a);
+    cI = pre * (8.0 / 3.0 - 3.0 * R / (4.0 * a));
+    cRR = pre / (4.0 * a * R);
+    dcI = -pre * 3.0 / (4.0 * a);
+    dcRR = -pre / (4.0 * a * R * R);
+  }
+}
+
+__global__ __launch_bounds__(kRpyThreads) void rpy_adjoint_kernel(
+    const double* __restrict__ x, const double* __restrict__ Db, int64_t ld, int N, double a,
+    double* __restrict__ xbar, double* __restrict__ hpart, DevState* __restrict__ st) {
+  const int i = blockIdx.x * kRpyThreads + threadIdx.x;
+  if (i >= N) return;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0, hs = 0.0;
+  bool coincident = false;
+  for (int j = 0; j < N; ++j) {
+    if (j == i) continue;
+    const double R[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
+                         x[3 * i + 2] - x[3 * j + 2]};
+    const double Rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    if (Rn == 0.0) {
+      coincident = true;
+      continue;
+    }
+    double B[3][3], Bij[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Bij[r][c] = Db[(3 * (int64_t)j + c) * ld + 3 * (int64_t)i + r];
+        B[r][c] = Bij[r][c] + Db[(3 * (int64_t)i + c) * ld + 3 * (int64_t)j + r];
+      }
+    double cI, cRR, dcI, dcRR;  // per unit h*
+    rpy_slopes(Rn, 1.0, a, cI, cRR, dcI, dcRR);
+    double BR[3], BtR[3], BijR[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      BR[r] = B[r][0] * R[0] + B[r][1] * R[1] + B[r][2] * R[2];
+      BtR[r] = B[0][r] * R[0] + B[1][r] * R[1] + B[2][r] * R[2];
+      BijR[r] = Bij[r][0] * R[0] + Bij[r][1] * R[1] + Bij[r][2] * R[2];
+    }
+    const double trB = B[0][0] + B[1][1] + B[2][2];
+    const double q = R[0] * BR[0] + R[1] * BR[1] + R[2] * BR[2];
+    const double s = (dcI * trB + dcRR * q) / Rn;
+    g0 += s * R[0] + cRR * (BR[0] + BtR[0]);
+    g1 += s * R[1] + cRR * (BR[1] + BtR[1]);
+    g2 += s * R[2] + cRR * (BR[2] + BtR[2]);
+    hs += cI * (Bij[0][0] + Bij[1][1] + Bij[2][2]) +
+          cRR * (R[0] * BijR[0] + R[1] * BijR[1] + R[2] * BijR[2]);
+  }
+  xbar[3 * i] = g0;
+  xbar[3 * i + 1] = g1;
+  xbar[3 * i + 2] = g2;
+  hpart[i] = hs;
+  if (coincident) st->status = BD_ERR_PARAM;
+}
+
+// d phi / d h* = sum over beads of the partials, in bead order; the
+// position gradient is scaled by h* here (the per-bead pass works per unit
+// h*).
+__global__ __launch_bounds__(kRpyThreads) void rpy_adjoint_finish_kernel(
+    const double* __restrict__ hpart, int N, double hstar, double* __restrict__ xbar,
+    double* __restrict__ hbar) {
+  __shared__ double red[kRpyThreads];
+  double s = 0.0;
+  const int t = threadIdx.x;
+  const int per = (N + kRpyThreads - 1) / kRpyThreads;
+  for (int q = 0; q < per; ++q) {
+    const int i = t * per + q;
+    if (i < N) s += hpart[i];
+  }
+  red[t] = s;
+  for (int e = t; e < 3 * N; e += kRpyThreads) xbar[e] *= hstar;
+  __syncthreads();
+  if (t == 0) {
+    double total = 0.0;
+    for (int w = 0; w < kRpyThreads; ++w) total += red[w];
+    *hbar = total;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_rpy_adjoint(hipStream_t s, const bd_params_t& p, const double* x,
+                              const double* Dbar, int64_t ld, double* xbar, double* hbar,
+                              double* hpart, DevState* st) {
+  const int N = p.n_beads;
+  BD_LAUNCH("rpy_adjoint", rpy_adjoint_kernel, dim3((N + kRpyThreads - 1) / kRpyThreads),
+            dim3(kRpyThreads), 0, s, x, Dbar, ld, N, p.a, xbar, hpart, st);
+  BD_LAUNCH("rpy_adjoint_finish", rpy_adjoint_finish_kernel, dim3(1), dim3(kRpyThreads), 0, s,
+            hpart, N, p.hstar, xbar, hbar);
+  return hipGetLastError();
+}
 
 hipError_t launch_rpy_assemble(hipStream_t s, const bd_params_t& p, const double* x, double* D,
                                int64_t ld, int fill) {
