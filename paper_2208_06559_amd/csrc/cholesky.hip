@@ -1328,9 +1328,10 @@ hipError_t factor_step(const CholCtx& c, hipStream_t s, int64_t k0, int64_t* wid
 
 }  // namespace
 
-// Right-looking blocked factorisation in steps of one or two panels
-// (step = 2 applies two panels per pass over the trailing matrix, halving
-// its HBM traffic per flop), with depth-1 lookahead: while the main stream
+// Right-looking blocked factorisation in steps of up to max_panels panels
+// (four while more than wide_rows rows remain, two after: a step of p
+// panels applies them in one pass over the trailing matrix, dividing its
+// HBM traffic per flop by p), with depth-1 lookahead: while the main stream
 // applies step k0 to the trailing matrix (all but the next step's tile
 // columns), the auxiliary stream updates those tile columns first, then
 // factors the next step's panels.  Events order the two streams; with
