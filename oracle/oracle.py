@@ -6,8 +6,8 @@ code with the HIP library or its Python binding.
 
 Every function mirrors one routine of ``oracle/bdo.c``, where the equations
 each follows are cited (arXiv 2208.06559, Sections 3-4), except
-``observables`` and ``rpy_assemble_adjoint``, which are written here in
-numpy from their definitions.
+``observables``, ``rpy_assemble_adjoint`` and ``brownian_adjoint``, which
+are written here in numpy from their definitions.
 """
 from __future__ import annotations
 
@@ -271,6 +271,16 @@ def rpy_assemble_adjoint(p: Params, x: np.ndarray, Dbar: np.ndarray):
             uI, uRR, _, _ = _rpy_coeffs_and_slopes(1.0, p.a, R)  # per unit h*
             hbar += uI * np.trace(B) + uRR * q
     return xbar, hbar
+
+
+def brownian_adjoint(p: Params, L: np.ndarray, xi: np.ndarray, ybar: np.ndarray):
+    """Adjoint of y = c_B L xi (L lower triangular, the noise term of Eq. 6
+    times dt): returns (Lbar, xibar) = (c_B tril(ybar xi^T), c_B L^T ybar),
+    the gradients of <ybar, y> in L (lower triangle only; L's upper part is
+    not a variable) and in xi."""
+    c = np.sqrt(6.0 * p.dt) if p.noise == NOISE_UNIFORM_PAPER else np.sqrt(2.0 * p.dt)
+    L = np.tril(np.asarray(L, dtype=np.float64))
+    return c * np.tril(np.outer(ybar, xi)), c * (L.T @ ybar)
 
 
 def run(p: Params, step0: int, nsteps: int, x: np.ndarray):
