@@ -134,6 +134,16 @@ bd_status_t bd_rpy_assemble_adjoint(bd_handle_t h, const bd_params_t* p, const d
                                     const double* d_Dbar, int64_t ld, double* d_xbar,
                                     double* d_hbar, void* d_ws, size_t ws_bytes);
 
+/* Adjoint of the noise product y = c_B B xi (bd_brownian): for the
+ * gradient ybar of a scalar in y, writes Lbar = c_B ybar xi^T on the lower
+ * triangle of d_Lbar (n x n column-major, ldb >= n; the strict upper part
+ * is not touched) and xibar = c_B B^T ybar to d_xibar (n).  d_L: the lower
+ * triangle of B (ld >= n); d_xi: the noise of the forward call (its
+ * d_xi_out).  n <= 65535 (BD_ERR_UNSUPPORTED above). */
+bd_status_t bd_brownian_adjoint(bd_handle_t h, const bd_params_t* p, const double* d_L,
+                                int64_t ld, const double* d_xi, const double* d_ybar,
+                                double* d_Lbar, int64_t ldb, double* d_xibar);
+
 /* In-place Cholesky D = B B^T (Eq. 10) of the lower triangle of d_A
  * (n x n column-major, ld >= n); B overwrites the lower triangle, the strict
  * upper triangle is not touched.  Blocked right-looking: FP64 diagonal

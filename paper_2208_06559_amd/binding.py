@@ -34,7 +34,7 @@ EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_
            "bd_profile_begin", "bd_profile_end", "bd_ensemble_workspace_size",
            "bd_ensemble_create", "bd_ensemble_step", "bd_ensemble_get_info",
            "bd_ensemble_destroy", "bd_step_fraenkel", "bd_observables",
-           "bd_rpy_assemble_adjoint")
+           "bd_rpy_assemble_adjoint", "bd_brownian_adjoint")
 
 
 class BdError(RuntimeError):
@@ -131,6 +131,7 @@ def lib():
         L.bd_step_fraenkel.argtypes = [vp, pp, C.c_double, C.c_int64, dp, C.c_int, vp, C.c_size_t]
         L.bd_observables.argtypes = [vp, C.c_int32, dp, vp, dp]
         L.bd_rpy_assemble_adjoint.argtypes = [vp, pp, dp, dp, C.c_int64, dp, dp, vp, C.c_size_t]
+        L.bd_brownian_adjoint.argtypes = [vp, pp, dp, C.c_int64, dp, dp, dp, C.c_int64, dp]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -268,6 +269,15 @@ class Handle:
                                              xbar.data_ptr(), hbar.data_ptr(), ws.data_ptr(),
                                              ws.numel() * 8), "bd_rpy_assemble_adjoint")
         return xbar, hbar
+
+    def brownian_adjoint(self, p: Params, L: torch.Tensor, ld: int, xi: torch.Tensor,
+                         ybar: torch.Tensor, Lbar: torch.Tensor, ldb: int, xibar: torch.Tensor):
+        n = 3 * p.n_beads
+        self._sync_stream()
+        _check(lib().bd_brownian_adjoint(self._h, C.byref(p), _dev_f64(L, "L", (n - 1) * ld + n),
+                                         ld, _dev_f64(xi, "xi", n), _dev_f64(ybar, "ybar", n),
+                                         _dev_f64(Lbar, "Lbar", (n - 1) * ldb + n), ldb,
+                                         _dev_f64(xibar, "xibar", n)), "bd_brownian_adjoint")
 
     def observables(self, x: torch.Tensor, n_beads) -> torch.Tensor:
         """(n_chains, 4) tensor: R_ee (3 components) and R_g^2 per chain of

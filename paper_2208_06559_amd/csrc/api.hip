@@ -403,6 +403,19 @@ bd_status_t bd_rpy_assemble_adjoint(bd_handle_t h, const bd_params_t* p, const d
                                            static_cast<double*>(d_ws), h->st));
 }
 
+bd_status_t bd_brownian_adjoint(bd_handle_t h, const bd_params_t* p, const double* d_L,
+                                int64_t ld, const double* d_xi, const double* d_ybar,
+                                double* d_Lbar, int64_t ldb, double* d_xibar) {
+  CallScope scope(h);
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!params_ok(p) || !d_L || !d_xi || !d_ybar || !d_Lbar || !d_xibar) return BD_ERR_PARAM;
+  const int64_t n = 3 * (int64_t)p->n_beads;
+  if (ld < n || ldb < n || n > 65535) return n > 65535 ? BD_ERR_UNSUPPORTED : BD_ERR_PARAM;
+  return hip_status(
+      bd::launch_brownian_adjoint(h->stream, *p, d_L, ld, d_xi, d_ybar, d_Lbar, ldb, d_xibar));
+}
+
 bd_status_t bd_observables(bd_handle_t h, int32_t n_chains, const double* d_x,
                            const int64_t* d_offsets, double* d_out) {
   CallScope scope(h);

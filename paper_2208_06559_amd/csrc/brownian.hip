@@ -151,9 +151,51 @@ __global__ __launch_bounds__(256) void predictor_batched_kernel(const ChainDesc*
                  k[7], k[8]);
 }
 
+// Adjoint of y = c L xi: Lbar(i, j) = c ybar_i xi_j on the lower triangle
+// (column j = blockIdx.y, rows from blockIdx.x), column-major with ldb.
+__global__ __launch_bounds__(256) void brownian_adjoint_l_kernel(const double* __restrict__ xi,
+                                                                  const double* __restrict__ ybar,
+                                                                  int64_t n, double c,
+                                                                  double* __restrict__ Lbar,
+                                                                  int64_t ldb) {
+  const int64_t j = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || i < j) return;
+  Lbar[j * ldb + i] = c * ybar[i] * xi[j];
+}
+
+// xibar_j = c sum_{i >= j} L(i, j) ybar_i: one wave per column j (its rows
+// contiguous), lane sums in row order, then a fixed butterfly.
+__global__ __launch_bounds__(256) void brownian_adjoint_xi_kernel(const double* __restrict__ L,
+                                                                   int64_t ld,
+                                                                   const double* __restrict__ ybar,
+                                                                   int64_t n, double c,
+                                                                   double* __restrict__ xibar) {
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= n) return;  // wave-uniform
+  double s = 0.0;
+  for (int64_t i = j + lane; i < n; i += 64) s += L[j * ld + i] * ybar[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) xibar[j] = c * s;
+}
+
 }  // namespace
 
 static int64_t trmv_tiles(int64_t n) { return (n + kTv - 1) / kTv; }
+
+hipError_t launch_brownian_adjoint(hipStream_t s, const bd_params_t& p, const double* L,
+                                   int64_t ld, const double* xi, const double* ybar,
+                                   double* Lbar, int64_t ldb, double* xibar) {
+  const int64_t n = 3 * (int64_t)p.n_beads;
+  const double c = (p.noise == BD_NOISE_UNIFORM_PAPER) ? sqrt(6.0 * p.dt) : sqrt(2.0 * p.dt);
+  BD_LAUNCH("brownian_adjoint_l", brownian_adjoint_l_kernel,
+            dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, xi, ybar, n, c, Lbar,
+            ldb);
+  BD_LAUNCH("brownian_adjoint_xi", brownian_adjoint_xi_kernel, dim3((unsigned)((n + 3) / 4)),
+            dim3(256), 0, s, L, ld, ybar, n, c, xibar);
+  return hipGetLastError();
+}
 
 size_t brownian_workspace_bytes(int64_t n) {
   const int64_t nt = trmv_tiles(n);

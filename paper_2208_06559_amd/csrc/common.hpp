@@ -55,6 +55,9 @@ hipError_t launch_brownian(hipStream_t s, const bd_params_t& p, int64_t step, co
                            int64_t ld, double* y, double* xi_out, void* ws);
 hipError_t launch_predictor(hipStream_t s, const bd_params_t& p, const double* x, const double* y,
                             double* xs);
+hipError_t launch_brownian_adjoint(hipStream_t s, const bd_params_t& p, const double* L,
+                                   int64_t ld, const double* xi, const double* ybar,
+                                   double* Lbar, int64_t ldb, double* xibar);
 
 // constrain.hip
 size_t constrain_workspace_bytes(int64_t n_beads);
