@@ -174,7 +174,8 @@ bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_
                          double* d_x_pred_inout, double* d_T_out, void* d_ws, size_t ws_bytes);
 
 /* One timestep of one chain: steps 1-5 above with noise counter `step`.
- * d_x_inout: N x 3, advanced in place. */
+ * d_x_inout: N x 3, advanced in place, or left unchanged when the step
+ * fails (non-positive pivot, tensions not converged; see bd_get_info). */
 bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d_x_inout,
                     bd_precision_t prec, void* d_ws, size_t ws_bytes);
 
@@ -242,7 +243,8 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
                                bd_ensemble_t* out);
 
 /* One timestep of every chain with noise counter `step`; d_x is advanced in
- * place.  A chain whose factorisation fails keeps its positions; its status
+ * place.  A chain whose step fails (non-positive pivot, tensions not
+ * converged) keeps its positions; its status
  * and those of the others are reported by bd_ensemble_get_info.  The call
  * synchronises the stream a few times during the tension solves. */
 bd_status_t bd_ensemble_step(bd_ensemble_t e, int64_t step);

@@ -96,10 +96,11 @@ __global__ void reset_state_kernel(DevState* st) {
   st->done = 0;
 }
 
-// x <- xs unless the factorisation failed (positions stay at x^t then).
+// x <- xs unless the step failed (non-positive pivot or no converged
+// tensions: positions stay at x^t then).
 __global__ void commit_positions_kernel(double* x, const double* xs, int64_t n,
                                         const DevState* st) {
-  if (st->status == BD_ERR_NOT_SPD) return;
+  if (st->status != BD_OK) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) x[e] = xs[e];
 }
@@ -121,7 +122,7 @@ __global__ void reset_states_kernel(DevState* st, int count) {
 
 __global__ void commit_positions_batched_kernel(const bd::ChainDesc* cd) {
   const bd::ChainDesc& c = cd[blockIdx.z];
-  if (c.st->status == BD_ERR_NOT_SPD) return;
+  if (c.st->status != BD_OK) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < c.n) c.x[e] = c.xs[e];
 }
@@ -412,6 +413,7 @@ bd_status_t bd_brownian_adjoint(bd_handle_t h, const bd_params_t* p, const doubl
   if (!params_ok(p) || !d_L || !d_xi || !d_ybar || !d_Lbar || !d_xibar) return BD_ERR_PARAM;
   const int64_t n = 3 * (int64_t)p->n_beads;
   if (ld < n || ldb < n || n > 65535) return n > 65535 ? BD_ERR_UNSUPPORTED : BD_ERR_PARAM;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
   return hip_status(
       bd::launch_brownian_adjoint(h->stream, *p, d_L, ld, d_xi, d_ybar, d_Lbar, ldb, d_xibar));
 }
@@ -422,6 +424,7 @@ bd_status_t bd_observables(bd_handle_t h, int32_t n_chains, const double* d_x,
   bd_status_t e = enter(h);
   if (e != BD_OK) return e;
   if (n_chains < 1 || n_chains > 2147483647 || !d_x || !d_offsets || !d_out) return BD_ERR_PARAM;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
   return hip_status(bd::launch_observables(h->stream, n_chains, d_x, d_offsets, d_out));
 }
 

@@ -151,17 +151,35 @@ __global__ __launch_bounds__(256) void predictor_batched_kernel(const ChainDesc*
                  k[7], k[8]);
 }
 
-// Adjoint of y = c L xi: Lbar(i, j) = c ybar_i xi_j on the lower triangle
-// (column j = blockIdx.y, rows from blockIdx.x), column-major with ldb.
+// Adjoint of y = c L xi: Lbar(i, j) = c ybar_i xi_j on the lower triangle,
+// column-major with ldb.  One workgroup per 64 x 64 tile of the lower
+// triangle (tile t = ti (ti + 1)/2 + tj, tj <= ti); lane r of wave w writes
+// row r of columns w, w + 4, ... (each column a coalesced 512-byte run).
+constexpr int kAdjTile = 64;
+
+__device__ __forceinline__ void tri_tile(int64_t t, int64_t& ti, int64_t& tj) {
+  int64_t r = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (r * (r + 1) / 2 > t) --r;           // the estimate may be one off either way
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  ti = r;
+  tj = t - r * (r + 1) / 2;
+}
+
 __global__ __launch_bounds__(256) void brownian_adjoint_l_kernel(const double* __restrict__ xi,
                                                                   const double* __restrict__ ybar,
                                                                   int64_t n, double c,
                                                                   double* __restrict__ Lbar,
                                                                   int64_t ldb) {
-  const int64_t j = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || i < j) return;
-  Lbar[j * ldb + i] = c * ybar[i] * xi[j];
+  int64_t ti, tj;
+  tri_tile(blockIdx.x, ti, tj);
+  const int64_t i = ti * kAdjTile + (threadIdx.x & 63);
+  if (i >= n) return;
+  const double cy = c * ybar[i];
+  for (int q = threadIdx.x >> 6; q < kAdjTile; q += 4) {
+    const int64_t j = tj * kAdjTile + q;
+    if (j > i) break;  // j grows with q: the rest of this lane's columns lie above the diagonal
+    Lbar[j * ldb + i] = cy * xi[j];
+  }
 }
 
 // xibar_j = c sum_{i >= j} L(i, j) ybar_i: one wave per column j (its rows
@@ -189,9 +207,9 @@ hipError_t launch_brownian_adjoint(hipStream_t s, const bd_params_t& p, const do
                                    double* Lbar, int64_t ldb, double* xibar) {
   const int64_t n = 3 * (int64_t)p.n_beads;
   const double c = (p.noise == BD_NOISE_UNIFORM_PAPER) ? sqrt(6.0 * p.dt) : sqrt(2.0 * p.dt);
-  BD_LAUNCH("brownian_adjoint_l", brownian_adjoint_l_kernel,
-            dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, s, xi, ybar, n, c, Lbar,
-            ldb);
+  const int64_t nt = (n + kAdjTile - 1) / kAdjTile;
+  BD_LAUNCH("brownian_adjoint_l", brownian_adjoint_l_kernel, dim3((unsigned)(nt * (nt + 1) / 2)),
+            dim3(256), 0, s, xi, ybar, n, c, Lbar, ldb);
   BD_LAUNCH("brownian_adjoint_xi", brownian_adjoint_xi_kernel, dim3((unsigned)((n + 3) / 4)),
             dim3(256), 0, s, L, ld, ybar, n, c, xibar);
   return hipGetLastError();

@@ -841,6 +841,17 @@ __global__ __launch_bounds__(kCtlThreads) void newton_controller_batched_kernel(
   newton_controller_body(carve(c.cons, c.N), c.xs, nullptr, c.N, c.dt, c.b, c.tol, c.maxit, c.st);
 }
 
+// States of `count` chains whose iteration the host stopped launching:
+// those not finished report non-convergence (their positions are then not
+// committed).
+__global__ void constrain_unfinished_kernel(DevState* st, int count) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < count && !st[c].done) {
+    if (st[c].status == BD_OK) st[c].status = BD_ERR_NO_CONVERGE;
+    st[c].done = 1;
+  }
+}
+
 }  // namespace
 
 size_t constrain_workspace_bytes(int64_t n_beads) { return carve_bytes((int)n_beads); }
@@ -885,8 +896,12 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
     if (host_state->done) break;
     batch = 4;
   }
-  if (pairs_hint && host_state->done)
+  if (!host_state->done) {
+    // the launch cap ended the iteration before the device did
+    BD_LAUNCH("constrain_unfinished", constrain_unfinished_kernel, dim3(1), dim3(64), 0, s, st, 1);
+  } else if (pairs_hint) {
     *pairs_hint = host_state->newton_iters + host_state->krylov_iters;
+  }
   return hipGetLastError();
 }
 
@@ -937,7 +952,10 @@ hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int coun
     if (all_done) break;
     batch = 4;
   }
-  if (pairs_hint && all_done) {
+  if (!all_done) {
+    BD_LAUNCH("constrain_unfinished", constrain_unfinished_kernel, dim3((count + 63) / 64),
+              dim3(64), 0, s, st, count);
+  } else if (pairs_hint) {
     int most = 0;
     for (int c = 0; c < count; ++c) {
       const int p = host_states[c].newton_iters + host_states[c].krylov_iters;

@@ -194,29 +194,41 @@ W = I.ENSEMBLE_SHEAR
 
 @pytest.mark.parametrize("prec,tol", [(B.PREC_FP64, 1e-10), (B.PREC_MIXED, 1e-6)])
 def test_ensemble_full_size(h, h_wide, prec, tol):
+    """Three steps of the 256-chain workload: after each, every chain's rods
+    within 1e-10 b; sampled chains (the smallest, the largest and two more)
+    bitwise equal to bd_step from the same state, and within the
+    single-chain tolerance of the oracle's step from that state."""
     sizes = I.ensemble_sizes(W.chains, seed=W.seed)
     spec = I.ensemble_chains(W, sizes)
     pgs = [B.make_params(d["n_beads"], dt=W.dt, kappa=d["kappa"], seed=d["seed"],
                          chain_id=d["chain_id"], hstar=W.hstar, a=W.a, b=W.b) for d in spec]
     xp = torch.tensor(np.concatenate([d["x"] for d in spec]), dtype=torch.float64, device=DEV)
     ens = B.Ensemble(h, pgs, xp, prec)
-    ens.step(0)
-    infos = ens.info()
-    assert all(i["status"] == B.OK for i in infos)
     xs = _split(xp, [(p, None, None) for p in pgs])
-    for c in range(len(spec)):
-        rods = torch.linalg.norm(xs[c][1:] - xs[c][:-1], dim=1)
-        assert (rods - W.b).abs().max().item() <= 1e-10, c
     order = np.argsort(sizes, kind="stable")
-    for c in sorted({int(order[0]), int(order[-1]), 17, 200}):
-        d = spec[c]
-        single = torch.tensor(d["x"], dtype=torch.float64, device=DEV)
-        h_wide.step(pgs[c], 0, single, prec)
-        assert h_wide.info() == infos[c]
-        assert torch.equal(single, xs[c]), c
-        po = o.make_params(d["n_beads"], dt=W.dt, kappa=d["kappa"], seed=d["seed"],
-                           chain_id=d["chain_id"], hstar=W.hstar, a=W.a, b=W.b)
-        xo, io = o.step(po, 0, d["x"])
-        assert io["status"] == o.OK
-        assert np.abs(xs[c].cpu().numpy() - xo).max() / W.b <= tol, c
+    sampled = sorted({int(order[0]), int(order[-1]), 17, 200})
+    worst = 0.0
+    for s in range(3):
+        before = {c: xs[c].cpu().numpy().copy() for c in sampled}
+        ens.step(s)
+        infos = ens.info()
+        assert all(i["status"] == B.OK for i in infos), s
+        for c in range(len(spec)):
+            rods = torch.linalg.norm(xs[c][1:] - xs[c][:-1], dim=1)
+            assert (rods - W.b).abs().max().item() <= 1e-10, (s, c)
+        for c in sampled:
+            d = spec[c]
+            single = torch.tensor(before[c], dtype=torch.float64, device=DEV)
+            h_wide.step(pgs[c], s, single, prec)
+            assert h_wide.info() == infos[c], (s, c)
+            assert torch.equal(single, xs[c]), (s, c)
+            po = o.make_params(d["n_beads"], dt=W.dt, kappa=d["kappa"], seed=d["seed"],
+                               chain_id=d["chain_id"], hstar=W.hstar, a=W.a, b=W.b)
+            xo, io = o.step(po, s, before[c])
+            assert io["status"] == o.OK
+            err = np.abs(xs[c].cpu().numpy() - xo).max() / W.b
+            assert err <= tol, (s, c, err)
+            worst = max(worst, err)
+    print(f"ensemble prec {prec}: 3 steps, sampled chains {sampled}, worst |dr|/b vs oracle "
+          f"{worst:.3e}", flush=True)
     ens.close()

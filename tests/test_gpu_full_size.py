@@ -17,9 +17,9 @@ at any size:
   L L^T - D is at most its Frobenius norm, so the bound
   ||L L^T - D||_F <= 1e-6 ||D||_F caps each sampled entry at
   1e-6 ||D||_F; the full residual is also formed with an FP64 GEMM;
-* one whole step (Eq. 6 with the rigid-rod solve) against the oracle's step
-  from the same state and seeds: FP64 within 1e-10 b, mixed within 1e-6 b,
-  rod lengths within 1e-10 b.
+* two whole steps (Eq. 6 with the rigid-rod solve), each against the
+  oracle's step from the same state and seeds: FP64 within 1e-10 b, mixed
+  within 1e-6 b, rod lengths within 1e-10 b.
 """
 import numpy as np
 import pytest
@@ -125,17 +125,22 @@ def test_cholesky_full_size(h, prec):
 
 
 def test_step_full_size(h):
+    """The first two steps of the workload, each from the oracle's state
+    (step 0 from the start, step 1 from the oracle's step-0 result)."""
     pg, po = _params()
-    x0 = W.initial()
-    xo, io = o.step(po, 0, x0)
-    assert io["status"] == o.OK
-    for prec, tol in ((B.PREC_FP64, 1e-10), (B.PREC_MIXED, 1e-6)):
-        xg = torch.tensor(x0, dtype=torch.float64, device=DEV)
-        h.step(pg, 0, xg, prec)
-        st = h.info()
-        assert st["status"] == B.OK, (prec, st)
-        xn = xg.cpu().numpy()
-        err = np.abs(xn - xo).max() / W.b
-        assert err <= tol, (prec, err)
-        rods = np.linalg.norm(np.diff(xn, axis=0), axis=1)
-        assert np.abs(rods - W.b).max() <= 1e-10, prec
+    x = W.initial()
+    for s in range(2):
+        xo, io = o.step(po, s, x)
+        assert io["status"] == o.OK
+        for prec, tol in ((B.PREC_FP64, 1e-10), (B.PREC_MIXED, 1e-6)):
+            xg = torch.tensor(x, dtype=torch.float64, device=DEV)
+            h.step(pg, s, xg, prec)
+            st = h.info()
+            assert st["status"] == B.OK, (s, prec, st)
+            xn = xg.cpu().numpy()
+            err = np.abs(xn - xo).max() / W.b
+            print(f"N = {N} step {s} prec {prec}: max |dr|/b vs oracle {err:.3e}", flush=True)
+            assert err <= tol, (s, prec, err)
+            rods = np.linalg.norm(np.diff(xn, axis=0), axis=1)
+            assert np.abs(rods - W.b).max() <= 1e-10, (s, prec)
+        x = xo
