@@ -161,6 +161,19 @@ bd_status_t bd_cholesky(bd_handle_t h, int64_t n, double* d_A, int64_t ld, bd_pr
 bd_status_t bd_brownian(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_L,
                         int64_t ld, double* d_y, double* d_xi_out, void* d_ws, size_t ws_bytes);
 
+/* bd_brownian without a workspace, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  The same kernels and results as bd_brownian; their
+ * scratch (xi and the per-tile partial sums, 4.8 MB) is a fixed device array
+ * of the library, one per GPU, held until the process ends, sized for
+ * n = 3N <= 12288 (BD_ERR_UNSUPPORTED above).  The call allocates nothing.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (two streams, two handles or two host threads at once) race and give
+ * wrong results; calls ordered on one stream are safe.  Arguments as for
+ * bd_brownian. */
+bd_status_t bd_brownian_noalloc(bd_handle_t h, const bd_params_t* p, int64_t step,
+                                const double* d_L, int64_t ld, double* d_y, double* d_xi_out);
+
 /* Rigid-rod constraint: tensions T_k along the rod directions u_k of d_x_old
  * such that x^{t+dt} = x* - dt D(x_old) Delta^T U T has |Q_k| = b for every
  * rod (the infinite-stiffness limit of the semi-implicit spring update of

@@ -34,7 +34,7 @@ EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_
            "bd_profile_begin", "bd_profile_end", "bd_ensemble_workspace_size",
            "bd_ensemble_create", "bd_ensemble_step", "bd_ensemble_get_info",
            "bd_ensemble_destroy", "bd_step_fraenkel", "bd_observables",
-           "bd_rpy_assemble_adjoint", "bd_brownian_adjoint")
+           "bd_rpy_assemble_adjoint", "bd_brownian_adjoint", "bd_brownian_noalloc")
 
 
 class BdError(RuntimeError):
@@ -132,6 +132,7 @@ def lib():
         L.bd_observables.argtypes = [vp, C.c_int32, dp, vp, dp]
         L.bd_rpy_assemble_adjoint.argtypes = [vp, pp, dp, dp, C.c_int64, dp, dp, vp, C.c_size_t]
         L.bd_brownian_adjoint.argtypes = [vp, pp, dp, C.c_int64, dp, dp, dp, C.c_int64, dp]
+        L.bd_brownian_noalloc.argtypes = [vp, pp, C.c_int64, dp, C.c_int64, dp, dp]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -227,6 +228,17 @@ class Handle:
         _check(lib().bd_brownian(self._h, C.byref(p), step, _dev_f64(L, "L", (n - 1) * ld + n), ld,
                                  _dev_f64(y, "y", n), xi_ptr, ws.data_ptr(), ws.numel()),
                "bd_brownian")
+
+    def brownian_noalloc(self, p: Params, step: int, L: torch.Tensor, ld: int, y: torch.Tensor,
+                         xi_out: torch.Tensor | None = None):
+        """bd_brownian_noalloc: the noise product with the library's fixed
+        scratch array in place of a workspace."""
+        n = 3 * p.n_beads
+        self._sync_stream()
+        xi_ptr = _dev_f64(xi_out, "xi_out", n) if xi_out is not None else None
+        _check(lib().bd_brownian_noalloc(self._h, C.byref(p), step,
+                                         _dev_f64(L, "L", (n - 1) * ld + n), ld,
+                                         _dev_f64(y, "y", n), xi_ptr), "bd_brownian_noalloc")
 
     def constrain(self, p: Params, x_old: torch.Tensor, x_pred: torch.Tensor,
                   T_out: torch.Tensor | None = None):

@@ -33,6 +33,7 @@ struct bd_handle_s {
   int step_panels;     // most Cholesky panels applied per pass over the trailing matrix
   int64_t wide_rows;   // steps of more than two panels while more rows than this remain
   bool tile_potrf;     // Cholesky diagonal blocks on matrix cores
+  void* scratch;       // this device's fixed scratch array (bd_brownian_noalloc)
 };
 
 namespace {
@@ -203,6 +204,7 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   h->pairs_hint = 0;
   h->aux = nullptr;
   h->ev[0] = h->ev[1] = h->ev[2] = h->ev[3] = nullptr;
+  h->scratch = nullptr;
   // BDRPY_STEP_PANELS=1 or 2 caps the panels per trailing pass (for
   // comparisons).  By default four panels share each pass while the
   // trailing matrix is large (more than BDRPY_WIDE_ROWS rows, default 4096),
@@ -216,6 +218,12 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   // kernel (for comparisons); by default they run on matrix cores.
   const char* pt = getenv("BDRPY_POTRF");
   h->tile_potrf = !(pt && pt[0] == 'r');
+  // the device address of this device's scratch array, looked up once per
+  // device with the device current
+  if (bd::brownian_scratch_init(device, &h->scratch) != hipSuccess) {
+    release(h);
+    return BD_ERR_HIP;
+  }
   if (hipMalloc(&h->st, sizeof(DevState)) != hipSuccess ||
       hipHostMalloc(&h->host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
     release(h);
@@ -308,6 +316,21 @@ bd_status_t bd_brownian(bd_handle_t h, const bd_params_t* p, int64_t step, const
   if (ld < n || ws_bytes < bd::brownian_workspace_bytes(n)) return BD_ERR_PARAM;
   if (reset(h) != hipSuccess) return BD_ERR_HIP;
   return hip_status(bd::launch_brownian(h->stream, *p, step, d_L, ld, d_y, d_xi_out, d_ws));
+}
+
+bd_status_t bd_brownian_noalloc(bd_handle_t h, const bd_params_t* p, int64_t step,
+                                const double* d_L, int64_t ld, double* d_y, double* d_xi_out) {
+  CallScope scope(h);
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!params_ok(p) || !d_L || !d_y) return BD_ERR_PARAM;
+  const int64_t n = 3 * (int64_t)p->n_beads;
+  if (ld < n) return BD_ERR_PARAM;
+  if (n > bd::brownian_scratch_max_n()) return BD_ERR_UNSUPPORTED;
+  if (!h->scratch) return BD_ERR_HIP;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
+  // the same kernels as bd_brownian, their workspace the fixed array
+  return hip_status(bd::launch_brownian(h->stream, *p, step, d_L, ld, d_y, d_xi_out, h->scratch));
 }
 
 bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_old,

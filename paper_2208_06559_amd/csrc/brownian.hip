@@ -11,6 +11,8 @@
 #include "profile.hpp"
 #include "philox.hpp"
 
+#include <mutex>
+
 namespace bd {
 
 namespace {
@@ -218,6 +220,40 @@ hipError_t launch_brownian_adjoint(hipStream_t s, const bd_params_t& p, const do
 size_t brownian_workspace_bytes(int64_t n) {
   const int64_t nt = trmv_tiles(n);
   return align_up(sizeof(double) * n, 256) + align_up(sizeof(double) * nt * n, 256);
+}
+
+// Allocation-free noise product: the workspace of launch_brownian (xi and
+// the per-tile partial sums) in a fixed device array sized for matrix order
+// n <= kScratchMaxN, one copy per GPU, kept until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr int64_t kScratchMaxN = 12288;
+constexpr int64_t kScratchDoubles =
+    (int64_t)(((kScratchMaxN * 8 + 255) / 256 * 256 +
+               ((kScratchMaxN + kTv - 1) / kTv * kScratchMaxN * 8 + 255) / 256 * 256) / 8);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static_assert(kScratchDoubles * 8 >= 8 * kScratchMaxN + 8 * 48 * kScratchMaxN,
+              "scratch holds xi and the partial sums at the largest n");
+
+constexpr int kMaxDevices = 64;
+static void* g_scratch_addr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+int64_t brownian_scratch_max_n() { return kScratchMaxN; }
+
+hipError_t brownian_scratch_init(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_brownian(hipStream_t s, const bd_params_t& p, int64_t step, const double* L,

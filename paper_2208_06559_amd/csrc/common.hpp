@@ -55,6 +55,11 @@ hipError_t launch_brownian(hipStream_t s, const bd_params_t& p, int64_t step, co
                            int64_t ld, double* y, double* xi_out, void* ws);
 hipError_t launch_predictor(hipStream_t s, const bd_params_t& p, const double* x, const double* y,
                             double* xs);
+// The device address of this device's fixed scratch array of the
+// allocation-free noise product (looked up once per device; the caller has
+// made `device` current), and the largest matrix order it holds.
+hipError_t brownian_scratch_init(int device, void** out);
+int64_t brownian_scratch_max_n();
 hipError_t launch_brownian_adjoint(hipStream_t s, const bd_params_t& p, const double* L,
                                    int64_t ld, const double* xi, const double* ybar,
                                    double* Lbar, int64_t ldb, double* xibar);
