@@ -6,8 +6,9 @@ code with the HIP library or its Python binding.
 
 Every function mirrors one routine of ``oracle/bdo.c``, where the equations
 each follows are cited (arXiv 2208.06559, Sections 3-4), except
-``observables``, ``rpy_assemble_adjoint`` and ``brownian_adjoint``, which
-are written here in numpy from their definitions.
+``observables``, ``kramers_stress``, ``rpy_assemble_adjoint`` and
+``brownian_adjoint``, which are written here in numpy from their
+definitions.
 """
 from __future__ import annotations
 
@@ -222,6 +223,37 @@ def observables(x: np.ndarray) -> np.ndarray:
     rcm = x.mean(axis=0)
     rg2 = np.sum((x - rcm) ** 2) / len(x)
     return np.concatenate([ree, [rg2]])
+
+
+def kramers_stress(x: np.ndarray, b: float, *, tensions=None, k_spring=None) -> np.ndarray:
+    """Kramers stress of one chain (Section 5, Eq. 28) and its first normal
+    stress difference (Eq. 29), as [tau_xx, tau_yy, tau_zz, tau_xy, tau_xz,
+    tau_yz, N1], in units of kT per chain.
+
+    tau = sum_k F_k Q_k^T - M I over the M = N - 1 connectors Q_k =
+    r_{k+1} - r_k, with F_k the connector's force along Q_k: the Fraenkel
+    spring force of Eq. 3, K (|Q_k| - b) Q_k / |Q_k| (k_spring = K), or for
+    rigid rods the tension T_k times Q_k / |Q_k| (tensions = T, length M).
+    The isotropic part enters with the sign that makes tau vanish at
+    equilibrium (the virial <Q F^T> = kT I per connector); N1 = tau_xx -
+    tau_yy does not depend on it.  Plain loop over connectors."""
+    x = np.asarray(x, dtype=np.float64)
+    if (tensions is None) == (k_spring is None):
+        raise ValueError("give exactly one of tensions (rigid rods) or k_spring (springs)")
+    M = len(x) - 1
+    S = np.zeros((3, 3))
+    for k in range(M):
+        q = x[k + 1] - x[k]
+        ql = float(np.sqrt(q @ q))
+        if tensions is not None:
+            mag = float(tensions[k])
+        else:
+            mag = float(k_spring) * (ql - b)
+        F = mag * q / ql
+        S += np.outer(F, q)
+    tau = S - M * np.eye(3)
+    return np.array([tau[0, 0], tau[1, 1], tau[2, 2], tau[0, 1], tau[0, 2], tau[1, 2],
+                     tau[0, 0] - tau[1, 1]])
 
 
 def _rpy_coeffs_and_slopes(hstar: float, a: float, R: float):
