@@ -219,6 +219,25 @@ bd_status_t bd_step_fraenkel(bd_handle_t h, const bd_params_t* p, double k_sprin
 bd_status_t bd_observables(bd_handle_t h, int32_t n_chains, const double* d_x,
                            const int64_t* d_offsets, double* d_out);
 
+/* Kramers stress (Section 5, Eq. 28) and first normal stress difference
+ * (Eq. 29) of n_chains chains packed in d_x as for bd_observables (d_x,
+ * d_offsets: the same layout; every chain at least two beads, not checked).
+ * Per chain, over its M = N - 1 connectors Q_k = r_{k+1} - r_k,
+ *   tau = sum_k F_k Q_k^T - M I,   N1 = tau_xx - tau_yy   (units of kT),
+ * with F_k the connector's force along Q_k: for rigid rods (d_T given)
+ * the tension T_k times Q_k/|Q_k|, d_T packing chain c's M tensions (as
+ * bd_constrain returns them, at the start-of-step positions) from index
+ * d_offsets[c] - c; for the paper's Fraenkel springs (d_T = NULL) the
+ * force of Eq. 3, K (|Q_k| - b) Q_k/|Q_k| with K = k_spring > 0.  The sign
+ * of the isotropic part is the one that makes tau vanish at equilibrium
+ * (<Q F^T> = kT I per connector); N1 does not depend on it.  d_out (device,
+ * 7 n_chains doubles) receives per chain tau_xx, tau_yy, tau_zz, tau_xy,
+ * tau_xz, tau_yz, N1; the ensemble average is the mean over chains.
+ * Asynchronous on the handle's stream. */
+bd_status_t bd_stress(bd_handle_t h, int32_t n_chains, const double* d_x,
+                      const int64_t* d_offsets, const double* d_T, double k_spring, double b,
+                      double* d_out);
+
 /* Synchronise the handle's stream and return the info of the last call. */
 bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out);
 

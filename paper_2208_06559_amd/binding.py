@@ -34,7 +34,8 @@ EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_
            "bd_profile_begin", "bd_profile_end", "bd_ensemble_workspace_size",
            "bd_ensemble_create", "bd_ensemble_step", "bd_ensemble_get_info",
            "bd_ensemble_destroy", "bd_step_fraenkel", "bd_observables",
-           "bd_rpy_assemble_adjoint", "bd_brownian_adjoint", "bd_brownian_noalloc")
+           "bd_rpy_assemble_adjoint", "bd_brownian_adjoint", "bd_brownian_noalloc",
+           "bd_stress")
 
 
 class BdError(RuntimeError):
@@ -133,6 +134,7 @@ def lib():
         L.bd_rpy_assemble_adjoint.argtypes = [vp, pp, dp, dp, C.c_int64, dp, dp, vp, C.c_size_t]
         L.bd_brownian_adjoint.argtypes = [vp, pp, dp, C.c_int64, dp, dp, dp, C.c_int64, dp]
         L.bd_brownian_noalloc.argtypes = [vp, pp, C.c_int64, dp, C.c_int64, dp, dp]
+        L.bd_stress.argtypes = [vp, C.c_int32, dp, vp, dp, C.c_double, C.c_double, dp]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -303,6 +305,26 @@ class Handle:
         self._sync_stream()
         _check(lib().bd_observables(self._h, len(counts), _dev_f64(x, "x", 3 * sum(counts)),
                                     off.data_ptr(), out.data_ptr()), "bd_observables")
+        return out
+
+    def stress(self, x: torch.Tensor, n_beads, *, tensions: torch.Tensor | None = None,
+               k_spring: float = 0.0, b: float = 1.0) -> torch.Tensor:
+        """(n_chains, 7) tensor: tau_xx, tau_yy, tau_zz, tau_xy, tau_xz,
+        tau_yz and N1 per chain (bd_stress); rigid rods when ``tensions``
+        (packed, N_c - 1 per chain) is given, else springs of stiffness
+        ``k_spring``."""
+        counts = [int(v) for v in n_beads]
+        if not counts or min(counts) < 2:
+            raise ValueError("n_beads: every chain needs at least two beads")
+        off = torch.tensor([0] + list(np.cumsum(counts)), dtype=torch.int64,
+                           device=f"cuda:{self.device}")
+        out = torch.empty((len(counts), 7), dtype=torch.float64, device=f"cuda:{self.device}")
+        t_ptr = (_dev_f64(tensions, "tensions", sum(counts) - len(counts))
+                 if tensions is not None else None)
+        self._sync_stream()
+        _check(lib().bd_stress(self._h, len(counts), _dev_f64(x, "x", 3 * sum(counts)),
+                               off.data_ptr(), t_ptr, float(k_spring), float(b), out.data_ptr()),
+               "bd_stress")
         return out
 
     def profile_begin(self):

@@ -451,6 +451,20 @@ bd_status_t bd_observables(bd_handle_t h, int32_t n_chains, const double* d_x,
   return hip_status(bd::launch_observables(h->stream, n_chains, d_x, d_offsets, d_out));
 }
 
+bd_status_t bd_stress(bd_handle_t h, int32_t n_chains, const double* d_x,
+                      const int64_t* d_offsets, const double* d_T, double k_spring, double b,
+                      double* d_out) {
+  CallScope scope(h);
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (n_chains < 1 || !d_x || !d_offsets || !d_out) return BD_ERR_PARAM;
+  if (!(b > 0.0) || !isfinite(b)) return BD_ERR_PARAM;
+  if (!d_T && (!(k_spring > 0.0) || !isfinite(k_spring))) return BD_ERR_PARAM;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
+  return hip_status(bd::launch_stress(h->stream, n_chains, d_x, d_offsets, d_T, k_spring, b,
+                                      d_out));
+}
+
 bd_status_t bd_get_info(bd_handle_t h, bd_info_t* out) {
   bd_status_t e = enter(h);
   if (e != BD_OK) return e;

@@ -77,6 +77,11 @@ hipError_t launch_dmatvec(hipStream_t s, const bd_params_t& p, const double* x, 
 // observables.hip
 hipError_t launch_observables(hipStream_t s, int32_t n_chains, const double* x,
                               const int64_t* off, double* out);
+// Kramers stress and N1 of packed chains: rigid rods when T (packed
+// tensions, chain c's at offset off[c] - c) is given, else springs of
+// stiffness K and rest length b.
+hipError_t launch_stress(hipStream_t s, int32_t n_chains, const double* x, const int64_t* off,
+                         const double* T, double K, double b, double* out);
 
 // fraenkel.hip
 int fraenkel_max_beads();
