@@ -6,9 +6,10 @@ code with the HIP library or its Python binding.
 
 Every function mirrors one routine of ``oracle/bdo.c``, where the equations
 each follows are cited (arXiv 2208.06559, Sections 3-4), except
-``observables``, ``kramers_stress``, ``rpy_assemble_adjoint`` and
-``brownian_adjoint``, which are written here in numpy from their
-definitions.
+``observables``, ``kramers_stress``, ``rpy_assemble_adjoint``,
+``brownian_adjoint``, ``cholesky_adjoint``, ``constrain_adjoint``,
+``step_adjoint``, ``mean_stretch`` and ``stretch_gradient``, which are
+written here in numpy from their definitions.
 """
 from __future__ import annotations
 
@@ -313,6 +314,168 @@ def brownian_adjoint(p: Params, L: np.ndarray, xi: np.ndarray, ybar: np.ndarray)
     c = np.sqrt(6.0 * p.dt) if p.noise == NOISE_UNIFORM_PAPER else np.sqrt(2.0 * p.dt)
     L = np.tril(np.asarray(L, dtype=np.float64))
     return c * np.tril(np.outer(ybar, xi)), c * (L.T @ ybar)
+
+
+def cholesky_adjoint(L: np.ndarray, Lbar: np.ndarray) -> np.ndarray:
+    """Reverse-mode derivative of the Cholesky factorisation A = L L^T
+    (Eq. 10) in the matrix form of Murray (2016): for a scalar phi with
+    gradient Lbar in the lower-triangular entries of L,
+        d phi = <P, dA>,  P = L^-T Phi(L^T Lbar) L^-1,
+    Phi taking the lower triangle with the diagonal halved; returned as the
+    symmetric Abar = (P + P^T)/2, the gradient for symmetric dA.  The two
+    triangular solves are general solves (numpy LU)."""
+    L = np.tril(np.asarray(L, dtype=np.float64))
+    X = L.T @ np.tril(np.asarray(Lbar, dtype=np.float64))
+    Phi = np.tril(X)
+    Phi[np.diag_indices_from(Phi)] *= 0.5
+    Y = np.linalg.solve(L.T, Phi)        # L^-T Phi
+    P = np.linalg.solve(L.T, Y.T).T      # Y L^-1
+    return 0.5 * (P + P.T)
+
+
+def _difference_operator(N: int) -> np.ndarray:
+    """(3(N-1) x 3N) matrix of the rod vectors: (Delta x)_k = x_{k+1} - x_k."""
+    M = N - 1
+    Dl = np.zeros((3 * M, 3 * N))
+    for k in range(M):
+        for al in range(3):
+            Dl[3 * k + al, 3 * (k + 1) + al] = 1.0
+            Dl[3 * k + al, 3 * k + al] = -1.0
+    return Dl
+
+
+def constrain_adjoint(p: Params, x_old: np.ndarray, x_new: np.ndarray, xbar: np.ndarray,
+                      D: np.ndarray | None = None) -> np.ndarray:
+    """Adjoint of the tension solve by the implicit-function theorem.  The
+    constraint step maps x* to x^{t+dt} = x* - dt D Delta^T U T with T
+    defined by g(T) = |Q_k|^2 - b^2 = 0, Q = Delta x^{t+dt} (U: the rod
+    directions at x_old, D = D(x_old)).  For the gradient xbar of a scalar
+    in x^{t+dt}, mu solves J^T mu = -dt U^T Delta D xbar with the dense
+    Jacobian J = dg/dT = -2 dt diag(Q)^T Delta D Delta^T U (numpy LU), and
+    the returned z = xbar - 2 Delta^T (Q mu) (N x 3) is the gradient of that
+    scalar in whatever x^{t+dt} depends on at fixed T (in x* it is z
+    itself)."""
+    N = p.n_beads
+    M = N - 1
+    dt = p.dt
+    x_old = np.asarray(x_old, dtype=np.float64)
+    if D is None:
+        D = np.array(rpy_assemble(p, x_old, FILL_FULL))
+    q = np.diff(x_old, axis=0)
+    u = q / np.linalg.norm(q, axis=1)[:, None]
+    Q = np.diff(np.asarray(x_new, dtype=np.float64), axis=0)
+    xb = np.asarray(xbar, dtype=np.float64).ravel()
+    Dl = _difference_operator(N)
+    U = np.zeros((3 * M, M))
+    Qm = np.zeros((3 * M, M))
+    for k in range(M):
+        U[3 * k:3 * k + 3, k] = u[k]
+        Qm[3 * k:3 * k + 3, k] = Q[k]
+    J = -2.0 * dt * Qm.T @ (Dl @ D @ Dl.T) @ U
+    rhs = -dt * U.T @ (Dl @ (D @ xb))
+    mu = np.linalg.solve(J.T, rhs)
+    return (xb - 2.0 * Dl.T @ (Qm @ mu)).reshape(N, 3)
+
+
+def mean_stretch(X: np.ndarray, b: float) -> float:
+    """Ensemble-mean fractional stretch of chains X (C x N x 3): the mean of
+    |r_{N-1} - r_0| / ((N - 1) b), the end-to-end length of Section 5 over
+    the contour length."""
+    X = np.asarray(X, dtype=np.float64)
+    N = X.shape[1]
+    return float(np.mean(np.linalg.norm(X[:, -1] - X[:, 0], axis=1)) / ((N - 1) * b))
+
+
+def stretch_gradient(ps, X0: np.ndarray, nsteps: int, K0: np.ndarray):
+    """Pathwise gradient of J = mean_stretch after nsteps rigid-rod steps of
+    the chains X0 (C x N x 3; chain c with parameters ps[c], noise fixed by
+    their seeds) with respect to h* and to the rate e of kappa = e K0 (each
+    ps[c] holds its own kappa; the derivative is taken along K0).  Every
+    state is kept; the adjoint runs the steps backwards with step_adjoint.
+    Returns (J, dJ/dh*, dJ/de)."""
+    X0 = np.asarray(X0, dtype=np.float64)
+    C_, N = X0.shape[0], X0.shape[1]
+    b = ps[0].b
+    Xf = np.zeros_like(X0)
+    gh = ge = 0.0
+    for c in range(C_):
+        states = [X0[c].copy()]
+        for s in range(nsteps):
+            xn, info = step(ps[c], s, states[-1])
+            if info["status"] != OK:
+                raise ValueError(f"chain {c} step {s}: status {info['status']}")
+            states.append(xn)
+        Xf[c] = states[-1]
+        R = states[-1][-1] - states[-1][0]
+        xbar = np.zeros((N, 3))
+        g = R / np.linalg.norm(R) / ((N - 1) * b * C_)
+        xbar[-1] += g
+        xbar[0] -= g
+        for s in range(nsteps - 1, -1, -1):
+            xbar, hb, kb = step_adjoint(ps[c], s, states[s], xbar)
+            gh += hb
+            ge += float(np.sum(kb * K0))
+    return mean_stretch(Xf, b), gh, ge
+
+
+def step_adjoint(p: Params, s: int, x: np.ndarray, xbar_next: np.ndarray):
+    """Reverse-mode derivative of one rigid-rod step (``step``, the scheme of
+    Eq. 6 with the tensions of the constraint solve) at fixed noise: for the
+    gradient xbar_next of a scalar in x^{t+dt}, returns (xbar, hbar, kbar),
+    its gradients in x^t (N x 3), h* and kappa (3 x 3).
+
+    The forward parts are recomputed with the oracle's own routines: D(x)
+    (Eqs. 7-9), L (Eq. 10), xi and y = c_B L xi, the predictor x* = x +
+    dt kappa x + y, the tensions T and x^{t+dt} = x* + dt D f, f_i = T_i u_i
+    - T_{i-1} u_{i-1}, u the rod directions at x^t.  T is defined
+    implicitly by g_k = |Q_k|^2 - b^2 = 0 with Q = Delta x^{t+dt}; by the
+    implicit-function theorem the step's gradient is that of x^{t+dt} at
+    fixed T applied to z = xbar_next - 2 Delta^T (Q mu), where mu solves
+    J^T mu = (d x^{t+dt}/dT)^T xbar_next with the dense Jacobian
+    J = dg/dT = -2 dt diag(Q)^T Delta D Delta^T U (numpy LU).  z is then
+    carried through x*, the product D f (in D and in u) and the noise
+    product (the Cholesky adjoint above, then the assembly's adjoint)."""
+    N = p.n_beads
+    M = N - 1
+    dt = p.dt
+    kap = np.array([p.kappa[e] for e in range(9)]).reshape(3, 3)
+    cB = np.sqrt(6.0 * dt) if p.noise == NOISE_UNIFORM_PAPER else np.sqrt(2.0 * dt)
+    x = np.asarray(x, dtype=np.float64)
+    xb = np.asarray(xbar_next, dtype=np.float64).reshape(N, 3)
+    # forward, recomputed
+    D = np.array(rpy_assemble(p, x, FILL_FULL))
+    L, info = cholesky(D)
+    if info != 0:
+        raise ValueError(f"bdo_cholesky info {info}")
+    L = np.tril(L)
+    y, xi = brownian(p, s, L)
+    xs = x + dt * x @ kap.T + y.reshape(N, 3)
+    xnew, T, inf = constrain(p, x, xs)
+    if inf["status"] != OK:
+        raise ValueError(f"bdo_constrain status {inf['status']}")
+    q = np.diff(x, axis=0)
+    ql = np.linalg.norm(q, axis=1)
+    u = q / ql[:, None]
+    f = np.zeros((N, 3))
+    f[:M] += T[:, None] * u
+    f[1:] -= T[:, None] * u
+    z = constrain_adjoint(p, x, xnew, xb, D=D).ravel()
+    # x^{t+dt} = x* + dt D(x) f(T, u(x)) at fixed T
+    Dbar = dt * np.outer(z, f.ravel())
+    fbar = (dt * D @ z).reshape(N, 3)
+    ubar = T[:, None] * (fbar[:M] - fbar[1:])
+    qbar = (ubar - u * np.sum(u * ubar, axis=1)[:, None]) / ql[:, None]
+    xbar = np.zeros((N, 3))
+    xbar[1:] += qbar
+    xbar[:M] -= qbar
+    # x* = x + dt kappa x + c_B L xi
+    zs = z.reshape(N, 3)
+    xbar += zs + dt * zs @ kap
+    kbar = dt * zs.T @ x
+    Lbar = cB * np.tril(np.outer(z, xi))
+    Dbar += cholesky_adjoint(L, Lbar)
+    xd, hbar = rpy_assemble_adjoint(p, x, Dbar)
+    return xbar + xd, float(hbar), kbar
 
 
 def run(p: Params, step0: int, nsteps: int, x: np.ndarray):
