@@ -72,7 +72,9 @@ typedef enum {
   BD_OP_CHOLESKY = 0,
   BD_OP_BROWNIAN = 1,
   BD_OP_CONSTRAIN = 2,
-  BD_OP_STEP = 3
+  BD_OP_STEP = 3,
+  BD_OP_CHOLESKY_ADJOINT = 4,
+  BD_OP_STEP_ADJOINT = 5
 } bd_op_t;
 
 /* Model and step parameters (Sections 3 and 5). */
@@ -152,6 +154,21 @@ bd_status_t bd_brownian_adjoint(bd_handle_t h, const bd_params_t* p, const doubl
  * A non-positive pivot sets potrf_info (see bd_get_info). */
 bd_status_t bd_cholesky(bd_handle_t h, int64_t n, double* d_A, int64_t ld, bd_precision_t prec,
                         void* d_ws, size_t ws_bytes);
+
+/* Adjoint of the factorisation (Eq. 10), in the matrix form of Murray
+ * (2016): for the gradient Lbar of a scalar phi in the lower-triangular
+ * entries of B (d_Lbar, n x n column-major, ldb >= n; its strict upper part
+ * is not read), writes to d_Abar (n x n, lda >= n, every element) the
+ * symmetric gradient of phi in A = B B^T,
+ *   Abar = (P + P^T)/2,  P = B^-T Phi(B^T Lbar) B^-1,
+ * Phi keeping the lower triangle with the diagonal halved, so that
+ * d phi = <Abar, dA> for every symmetric dA.  d_L: the lower triangle of B
+ * (bd_cholesky's output; the strict upper part is not read).  FP64 on
+ * matrix cores; d_ws: bd_workspace_size(BD_OP_CHOLESKY_ADJOINT, n, FP64)
+ * bytes.  n <= 65535. */
+bd_status_t bd_cholesky_adjoint(bd_handle_t h, int64_t n, const double* d_L, int64_t ld,
+                                const double* d_Lbar, int64_t ldb, double* d_Abar, int64_t lda,
+                                void* d_ws, size_t ws_bytes);
 
 /* y = c_B B xi: the Brownian term of Eq. 6 times dt.  xi_e for e = 3i+alpha
  * comes from Philox4x64-10 with key (seed, chain_id) and counter

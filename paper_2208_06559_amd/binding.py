@@ -25,6 +25,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 NOISE_GAUSSIAN, NOISE_UNIFORM_PAPER = 0, 1
 FILL_LOWER, FILL_FULL = 0, 1
 OP_CHOLESKY, OP_BROWNIAN, OP_CONSTRAIN, OP_STEP = 0, 1, 2, 3
+OP_CHOLESKY_ADJOINT, OP_STEP_ADJOINT = 4, 5
 
 STATUS_NAMES = {0: "BD_OK", 1: "BD_ERR_PARAM", 2: "BD_ERR_NOT_SPD", 3: "BD_ERR_NO_CONVERGE",
                 4: "BD_ERR_HIP", 5: "BD_ERR_ALLOC", 6: "BD_ERR_UNSUPPORTED"}
@@ -35,7 +36,7 @@ EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_
            "bd_ensemble_create", "bd_ensemble_step", "bd_ensemble_get_info",
            "bd_ensemble_destroy", "bd_step_fraenkel", "bd_observables",
            "bd_rpy_assemble_adjoint", "bd_brownian_adjoint", "bd_brownian_noalloc",
-           "bd_stress")
+           "bd_stress", "bd_cholesky_adjoint")
 
 
 class BdError(RuntimeError):
@@ -135,6 +136,8 @@ def lib():
         L.bd_brownian_adjoint.argtypes = [vp, pp, dp, C.c_int64, dp, dp, dp, C.c_int64, dp]
         L.bd_brownian_noalloc.argtypes = [vp, pp, C.c_int64, dp, C.c_int64, dp, dp]
         L.bd_stress.argtypes = [vp, C.c_int32, dp, vp, dp, C.c_double, C.c_double, dp]
+        L.bd_cholesky_adjoint.argtypes = [vp, C.c_int64, dp, C.c_int64, dp, C.c_int64, dp,
+                                          C.c_int64, vp, C.c_size_t]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -230,6 +233,17 @@ class Handle:
         _check(lib().bd_brownian(self._h, C.byref(p), step, _dev_f64(L, "L", (n - 1) * ld + n), ld,
                                  _dev_f64(y, "y", n), xi_ptr, ws.data_ptr(), ws.numel()),
                "bd_brownian")
+
+    def cholesky_adjoint(self, n: int, L: torch.Tensor, ld: int, Lbar: torch.Tensor, ldb: int,
+                         Abar: torch.Tensor, lda: int):
+        """bd_cholesky_adjoint: Abar (every element) from B (lower of L) and
+        Lbar (lower), all (n, ld) column-major buffers."""
+        ws = self.workspace(OP_CHOLESKY_ADJOINT, n)
+        self._sync_stream()
+        _check(lib().bd_cholesky_adjoint(self._h, n, _dev_f64(L, "L", (n - 1) * ld + n), ld,
+                                         _dev_f64(Lbar, "Lbar", (n - 1) * ldb + n), ldb,
+                                         _dev_f64(Abar, "Abar", (n - 1) * lda + n), lda,
+                                         ws.data_ptr(), ws.numel()), "bd_cholesky_adjoint")
 
     def brownian_noalloc(self, p: Params, step: int, L: torch.Tensor, ld: int, y: torch.Tensor,
                          xi_out: torch.Tensor | None = None):

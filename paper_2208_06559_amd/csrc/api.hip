@@ -87,6 +87,39 @@ StepLayout step_layout(int64_t n, bd_precision_t prec, bool batched = false) {
   return L;
 }
 
+// Workspace of bd_step_adjoint: the forward step's own layout, then the
+// adjoint's buffers (three n x ld matrices: Lbar, Dbar and the Cholesky
+// adjoint's scratch of three more), z, the forward's xi, T and f.
+struct StepAdjointLayout {
+  size_t fwd, lbar, dbar, cadj, z, xi, T, xnew, hpart, total;
+};
+
+StepAdjointLayout step_adjoint_layout(int64_t n) {
+  StepAdjointLayout L;
+  const size_t mat = bd::align_up(sizeof(double) * (size_t)step_ld(n) * (size_t)n, 256);
+  size_t off = 0;
+  L.fwd = off;
+  off += step_layout(n, BD_PREC_FP64).total;
+  L.lbar = off;
+  off += mat;
+  L.dbar = off;
+  off += mat;
+  L.cadj = off;
+  off += bd::align_up(bd::cholesky_adjoint_workspace_bytes(n), 256);
+  L.z = off;
+  off += bd::align_up(sizeof(double) * n, 256);
+  L.xi = off;
+  off += bd::align_up(sizeof(double) * n, 256);
+  L.T = off;
+  off += bd::align_up(sizeof(double) * n, 256);
+  L.xnew = off;
+  off += bd::align_up(sizeof(double) * n, 256);
+  L.hpart = off;
+  off += bd::align_up(sizeof(double) * n, 256);
+  L.total = off;
+  return L;
+}
+
 __global__ void reset_state_kernel(DevState* st) {
   st->status = BD_OK;
   st->newton_iters = 0;
@@ -278,6 +311,13 @@ bd_status_t bd_workspace_size(bd_op_t op, int64_t n, bd_precision_t prec, size_t
       if (n % 3 || n < 6) return BD_ERR_PARAM;
       *bytes = step_layout(n, prec).total;
       return BD_OK;
+    case BD_OP_CHOLESKY_ADJOINT:
+      *bytes = bd::cholesky_adjoint_workspace_bytes(n);
+      return BD_OK;
+    case BD_OP_STEP_ADJOINT:
+      if (n % 3 || n < 6) return BD_ERR_PARAM;
+      *bytes = step_adjoint_layout(n).total;
+      return BD_OK;
   }
   return BD_ERR_PARAM;
 }
@@ -304,6 +344,20 @@ bd_status_t bd_cholesky(bd_handle_t h, int64_t n, double* d_A, int64_t ld, bd_pr
   if (reset(h) != hipSuccess) return BD_ERR_HIP;
   return hip_status(bd::launch_cholesky(h->stream, h->aux, h->ev, n, d_A, ld, prec, d_ws, h->st,
                                               h->step_panels, h->wide_rows, h->tile_potrf));
+}
+
+bd_status_t bd_cholesky_adjoint(bd_handle_t h, int64_t n, const double* d_L, int64_t ld,
+                                const double* d_Lbar, int64_t ldb, double* d_Abar, int64_t lda,
+                                void* d_ws, size_t ws_bytes) {
+  CallScope scope(h);
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (n < 1 || n > 65535 || !d_L || !d_Lbar || !d_Abar || !d_ws) return BD_ERR_PARAM;
+  if (ld < n || ldb < n || lda < n) return BD_ERR_PARAM;
+  if (ws_bytes < bd::cholesky_adjoint_workspace_bytes(n)) return BD_ERR_PARAM;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
+  return hip_status(bd::launch_cholesky_adjoint(h->stream, n, d_L, ld, 0, d_Lbar, ldb, 0, d_Abar,
+                                                lda, 0, 1.0, 0.0, 1, d_ws));
 }
 
 bd_status_t bd_brownian(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_L,

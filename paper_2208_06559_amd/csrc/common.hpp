@@ -49,6 +49,13 @@ hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int
                            int64_t ld, bd_precision_t prec, void* ws, DevState* st,
                            int max_panels, int64_t wide_rows, bool tile_potrf);
 
+// adjoint.hip
+size_t cholesky_adjoint_workspace_bytes(int64_t n);
+hipError_t launch_cholesky_adjoint(hipStream_t s, int64_t n, const double* L, int64_t ld,
+                                   int64_t sL, const double* Lbar, int64_t ldb, int64_t sLb,
+                                   double* Abar, int64_t lda, int64_t sAb, double alpha,
+                                   double beta, int batch, void* ws);
+
 // brownian.hip
 size_t brownian_workspace_bytes(int64_t n);
 hipError_t launch_brownian(hipStream_t s, const bd_params_t& p, int64_t step, const double* L,

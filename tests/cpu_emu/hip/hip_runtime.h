@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <type_traits>
 using std::sqrt; using std::fabs; using std::fma; using std::isinf; using std::isnan;
+using std::min; using std::max;
 #define __global__
 #define __device__
 #define __host__

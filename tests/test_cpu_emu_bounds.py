@@ -100,3 +100,18 @@ def test_batched_constrain_accesses_in_bounds(cbemu):
                        text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-3000:]
     assert "status 0" in r.stdout and "done 6" in r.stdout
+
+
+@pytest.fixture(scope="module")
+def aemu(tmp_path_factory):
+    return _build(tmp_path_factory, "adjoint_emu")
+
+
+# The Cholesky adjoint: ragged last blocks, exact multiples of the tile,
+# several join levels, padded leading dimensions, a batch of two.
+@pytest.mark.parametrize("n,ld_pad", [(1, 0), (5, 2), (64, 0), (65, 1), (127, 0), (128, 3),
+                                      (129, 0), (200, 5), (321, 0)])
+def test_cholesky_adjoint_accesses_in_bounds(aemu, n, ld_pad):
+    r = subprocess.run([aemu, str(n), str(ld_pad)], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, (n, ld_pad, r.stderr[-3000:])
+    assert "status 0" in r.stdout
