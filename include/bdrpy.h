@@ -203,6 +203,41 @@ bd_status_t bd_brownian_noalloc(bd_handle_t h, const bd_params_t* p, int64_t ste
 bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_old,
                          double* d_x_pred_inout, double* d_T_out, void* d_ws, size_t ws_bytes);
 
+/* Adjoint of the tension solve (bd_constrain), by the implicit-function
+ * theorem.  The constraint maps x* to x^{t+dt} = x* - dt D Delta^T U T with
+ * T fixed by g_k = |Q_k|^2 - b^2 = 0, Q = Delta x^{t+dt} (U: the rod
+ * directions of d_x_old, D = D(x_old)).  For the gradient d_xbar (N x 3) of
+ * a scalar in x^{t+dt} (d_x_new, bd_constrain's output), writes
+ *   z = xbar - 2 Delta^T (Q mu),  J^T mu = -dt U^T Delta D xbar,
+ * with J = dg/dT = -2 dt diag(Q)^T Delta D Delta^T U, to d_z (N x 3): the
+ * gradient of that scalar in x* (and in anything x^{t+dt} depends on at
+ * fixed T).  J^T mu = rhs is solved by GMRES right-preconditioned with the
+ * tridiagonal part of J^T (J with u and Q exchanged), products with D
+ * matrix-free, to a residual of newton_tol |rhs| (BD_ERR_NO_CONVERGE in
+ * bd_get_info otherwise).  d_ws: bd_workspace_size(BD_OP_CONSTRAIN, 3N)
+ * bytes; N <= 4097.  Synchronises the stream a few times, as bd_constrain. */
+bd_status_t bd_constrain_adjoint(bd_handle_t h, const bd_params_t* p, const double* d_x_old,
+                                 const double* d_x_new, const double* d_xbar, double* d_z,
+                                 void* d_ws, size_t ws_bytes);
+
+/* Adjoint of one FP64 step (bd_step at BD_PREC_FP64 with the same
+ * arguments), at fixed noise: for the gradient d_xbar of a scalar in
+ * x^{t+dt}, overwrites d_xbar with its gradient in x^t (d_x, N x 3, not
+ * modified) and adds its gradients in h* to d_hbar[0] and in kappa
+ * (row-major) to d_kbar[0..8].  The forward step is recomputed from d_x
+ * (D, B, xi, y, x*, T, x^{t+dt}); then the tension solve's adjoint gives z,
+ * the gradient in x^{t+dt} at fixed T, and z is carried back through
+ * x^{t+dt} = x* + dt D(x) f(T, u(x)) (Dbar = dt z f^T and the rod
+ * directions), through x* = x + dt kappa x + c_B B xi (Lbar = c_B z xi^T),
+ * the factorisation (bd_cholesky_adjoint's Abar added into Dbar) and the
+ * assembly (bd_rpy_assemble_adjoint of Dbar, Eqs. 7-9).  d_ws:
+ * bd_workspace_size(BD_OP_STEP_ADJOINT, 3N, FP64) bytes (about four n x n
+ * matrices plus bd_step's workspace); N <= 4097.  Status (pivot, tension or
+ * adjoint non-convergence, coincident beads) via bd_get_info. */
+bd_status_t bd_step_adjoint(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_x,
+                            double* d_xbar, double* d_hbar, double* d_kbar, void* d_ws,
+                            size_t ws_bytes);
+
 /* One timestep of one chain: steps 1-5 above with noise counter `step`.
  * d_x_inout: N x 3, advanced in place, or left unchanged when the step
  * fails (non-positive pivot, tensions not converged; see bd_get_info). */

@@ -36,7 +36,8 @@ EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_
            "bd_ensemble_create", "bd_ensemble_step", "bd_ensemble_get_info",
            "bd_ensemble_destroy", "bd_step_fraenkel", "bd_observables",
            "bd_rpy_assemble_adjoint", "bd_brownian_adjoint", "bd_brownian_noalloc",
-           "bd_stress", "bd_cholesky_adjoint")
+           "bd_stress", "bd_cholesky_adjoint", "bd_constrain_adjoint",
+           "bd_step_adjoint")
 
 
 class BdError(RuntimeError):
@@ -138,6 +139,8 @@ def lib():
         L.bd_stress.argtypes = [vp, C.c_int32, dp, vp, dp, C.c_double, C.c_double, dp]
         L.bd_cholesky_adjoint.argtypes = [vp, C.c_int64, dp, C.c_int64, dp, C.c_int64, dp,
                                           C.c_int64, vp, C.c_size_t]
+        L.bd_constrain_adjoint.argtypes = [vp, pp, dp, dp, dp, dp, vp, C.c_size_t]
+        L.bd_step_adjoint.argtypes = [vp, pp, C.c_int64, dp, dp, dp, dp, vp, C.c_size_t]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -244,6 +247,29 @@ class Handle:
                                          _dev_f64(Lbar, "Lbar", (n - 1) * ldb + n), ldb,
                                          _dev_f64(Abar, "Abar", (n - 1) * lda + n), lda,
                                          ws.data_ptr(), ws.numel()), "bd_cholesky_adjoint")
+
+    def constrain_adjoint(self, p: Params, x_old: torch.Tensor, x_new: torch.Tensor,
+                          xbar: torch.Tensor, z: torch.Tensor):
+        """bd_constrain_adjoint: z = xbar - 2 Delta^T (Q mu) (N x 3)."""
+        n = 3 * p.n_beads
+        ws = self.workspace(OP_CONSTRAIN, n)
+        self._sync_stream()
+        _check(lib().bd_constrain_adjoint(self._h, C.byref(p), _dev_f64(x_old, "x_old", n),
+                                          _dev_f64(x_new, "x_new", n), _dev_f64(xbar, "xbar", n),
+                                          _dev_f64(z, "z", n), ws.data_ptr(), ws.numel()),
+               "bd_constrain_adjoint")
+
+    def step_adjoint(self, p: Params, step: int, x: torch.Tensor, xbar: torch.Tensor,
+                     hbar: torch.Tensor, kbar: torch.Tensor):
+        """bd_step_adjoint: xbar (gradient in x^{t+dt}) becomes the gradient in
+        x^t; the gradients in h* and kappa are added to hbar (1) and kbar (9)."""
+        n = 3 * p.n_beads
+        ws = self.workspace(OP_STEP_ADJOINT, n)
+        self._sync_stream()
+        _check(lib().bd_step_adjoint(self._h, C.byref(p), step, _dev_f64(x, "x", n),
+                                     _dev_f64(xbar, "xbar", n), _dev_f64(hbar, "hbar", 1),
+                                     _dev_f64(kbar, "kbar", 9), ws.data_ptr(), ws.numel()),
+               "bd_step_adjoint")
 
     def brownian_noalloc(self, p: Params, step: int, L: torch.Tensor, ld: int, y: torch.Tensor,
                          xi_out: torch.Tensor | None = None):

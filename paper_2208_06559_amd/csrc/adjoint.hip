@@ -36,6 +36,10 @@ constexpr int kGThreads = 256;
 
 enum : int32_t { G_TA = 1, G_TB = 2, G_MA = 4, G_MB = 8, G_LOWC = 16 };
 
+struct Kappa {
+  double k[9];  // row-major: velocity v = kappa . r
+};
+
 // C = alpha op(A) op(B) + beta C on sub-blocks of column-major matrices of
 // order nmat.  Origins (row, column) are in stored coordinates; for op(X) =
 // X^T the stored block is k x m (A) or n x k (B).  Grid y = pair index: every
@@ -226,7 +230,144 @@ GemmOp gemm_op(const double* A, int64_t lda, const double* B, int64_t ldb, doubl
 
 int64_t adj_ld(int64_t n) { return (n + 63) / 64 * 64; }
 
+// ---- local parts of the step adjoint (one rigid-rod step, Eq. 6 with the
+// constraint tensions): x^{t+dt} = x* + dt D(x) f, f_i = T_i u_i -
+// T_{i-1} u_{i-1}, u_k = q_k/|q_k|, q_k = x_{k+1} - x_k, x* = x + dt kappa x
+// + y.  z is the tension solve's adjoint (the gradient in x^{t+dt} at fixed
+// T, equal to the gradient in x*).
+
+__device__ __forceinline__ void rod_dir(const double* __restrict__ x, int k, double u[3],
+                                        double& len) {
+  const double q0 = x[3 * (k + 1)] - x[3 * k], q1 = x[3 * (k + 1) + 1] - x[3 * k + 1],
+               q2 = x[3 * (k + 1) + 2] - x[3 * k + 2];
+  len = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+  u[0] = q0 / len;
+  u[1] = q1 / len;
+  u[2] = q2 / len;
+}
+
+__global__ __launch_bounds__(256) void rod_forces_kernel(const double* __restrict__ x,
+                                                         const double* __restrict__ T, int N,
+                                                         double* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double ui[3] = {0.0, 0.0, 0.0}, um[3] = {0.0, 0.0, 0.0}, len;
+  const double ti = (i < N - 1) ? T[i] : 0.0, tm = (i > 0) ? T[i - 1] : 0.0;
+  if (i < N - 1) rod_dir(x, i, ui, len);
+  if (i > 0) rod_dir(x, i - 1, um, len);
+#pragma unroll
+  for (int al = 0; al < 3; ++al) f[3 * i + al] = ti * ui[al] - tm * um[al];
+}
+
+// Dbar(a, b) = c z_a f_b, every element (column-major, a contiguous)
+__global__ __launch_bounds__(256) void rank1_kernel(const double* __restrict__ z,
+                                                    const double* __restrict__ f, double c,
+                                                    int64_t n, double* __restrict__ Dbar,
+                                                    int64_t ld) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = blockIdx.y;
+  if (a >= n) return;
+  Dbar[a + b * ld] = c * z[a] * f[b];
+}
+
+constexpr int kLocThreads = 256;
+
+// xbar = (u part) + z + dt z kappa; kbar += dt sum_i z_i x_i^T.  Dz = D z
+// (matrix-free product), so fbar = dt Dz and ubar_k = T_k (fbar_k -
+// fbar_{k+1}); qbar_k = (I - u_k u_k^T) ubar_k / |q_k| moves bead k + 1 by
+// +qbar_k and bead k by -qbar_k.  One workgroup; kappa's gradient by
+// fixed-order block sums.
+__global__ __launch_bounds__(kLocThreads) void step_adjoint_local_kernel(
+    const double* __restrict__ x, const double* __restrict__ T, const double* __restrict__ z,
+    const double* __restrict__ Dz, int N, double dt, Kappa kap, double* __restrict__ xbar,
+    double* __restrict__ kbar) {
+  __shared__ double red[kLocThreads / 64][9];
+  const int tid = threadIdx.x;
+  double kb[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) kb[e] = 0.0;
+  for (int i = tid; i < N; i += kLocThreads) {
+    double g[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      // z_i + dt (z_i kappa)_a = z_ia + dt sum_c z_ic kappa_ca
+      g[a] = z[3 * i + a] + dt * (z[3 * i] * kap.k[a] + z[3 * i + 1] * kap.k[3 + a] +
+                                  z[3 * i + 2] * kap.k[6 + a]);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) kb[3 * a + b] += z[3 * i + a] * x[3 * i + b];
+    }
+    // rods i-1 (bead i is its second end) and i (its first end)
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int k = (side == 0) ? i - 1 : i;
+      if (k < 0 || k >= N - 1) continue;
+      double u[3], len;
+      rod_dir(x, k, u, len);
+      double ub[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) ub[a] = T[k] * dt * (Dz[3 * k + a] - Dz[3 * (k + 1) + a]);
+      const double uu = u[0] * ub[0] + u[1] * ub[1] + u[2] * ub[2];
+      const double sgn = (side == 0) ? 1.0 : -1.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) g[a] += sgn * (ub[a] - u[a] * uu) / len;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xbar[3 * i + a] = g[a];
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    double v = kb[e];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6][e] = v;
+  }
+  __syncthreads();
+  if (tid < 9) {
+    double v = 0.0;
+    for (int w = 0; w < kLocThreads / 64; ++w) v += red[w][tid];
+    kbar[tid] += dt * v;
+  }
+}
+
+__global__ __launch_bounds__(256) void step_adjoint_finish_kernel(int64_t n,
+                                                                  const double* __restrict__ xbD,
+                                                                  const double* __restrict__ hstep,
+                                                                  double* __restrict__ xbar,
+                                                                  double* __restrict__ hbar) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) xbar[e] += xbD[e];
+  if (e == 0) *hbar += *hstep;
+}
+
 }  // namespace
+
+hipError_t launch_rod_forces(hipStream_t s, const double* x, const double* T, int N, double* f) {
+  BD_LAUNCH("rod_forces", rod_forces_kernel, dim3((N + 255) / 256), dim3(256), 0, s, x, T, N, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank1(hipStream_t s, const double* z, const double* f, double c, int64_t n,
+                        double* Dbar, int64_t ld) {
+  BD_LAUNCH("rank1", rank1_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0,
+            s, z, f, c, n, Dbar, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_adjoint_local(hipStream_t s, const bd_params_t& p, const double* x,
+                                     const double* T, const double* z, const double* Dz,
+                                     double* xbar, double* kbar) {
+  Kappa kap;
+  for (int e = 0; e < 9; ++e) kap.k[e] = p.kappa[e];
+  BD_LAUNCH("step_adjoint_local", step_adjoint_local_kernel, dim3(1), dim3(kLocThreads), 0, s, x,
+            T, z, Dz, p.n_beads, p.dt, kap, xbar, kbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_adjoint_finish(hipStream_t s, int64_t n, const double* xbD,
+                                      const double* hstep, double* xbar, double* hbar) {
+  BD_LAUNCH("step_adjoint_finish", step_adjoint_finish_kernel, dim3((unsigned)((n + 255) / 256)),
+            dim3(256), 0, s, n, xbD, hstep, xbar, hbar);
+  return hipGetLastError();
+}
 
 size_t cholesky_adjoint_workspace_bytes(int64_t n) {
   return 3 * align_up(sizeof(double) * (size_t)adj_ld(n) * (size_t)n, 256);

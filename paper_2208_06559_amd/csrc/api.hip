@@ -87,16 +87,18 @@ StepLayout step_layout(int64_t n, bd_precision_t prec, bool batched = false) {
   return L;
 }
 
-// Workspace of bd_step_adjoint: the forward step's own layout, then the
-// adjoint's buffers (three n x ld matrices: Lbar, Dbar and the Cholesky
-// adjoint's scratch of three more), z, the forward's xi, T and f.
+// Workspace of bd_step_adjoint: the forward step's own layout (its D
+// holds B after the factorisation, its x* the new positions), then Lbar,
+// Dbar, the Cholesky adjoint's scratch, and vectors of n: z, xi, T, f,
+// D z, the assembly adjoint's gradient, its h* partial sums (N) and h*.
 struct StepAdjointLayout {
-  size_t fwd, lbar, dbar, cadj, z, xi, T, xnew, hpart, total;
+  size_t fwd, lbar, dbar, cadj, z, xi, T, f, dz, xbd, hpart, hstep, total;
 };
 
 StepAdjointLayout step_adjoint_layout(int64_t n) {
   StepAdjointLayout L;
   const size_t mat = bd::align_up(sizeof(double) * (size_t)step_ld(n) * (size_t)n, 256);
+  const size_t vec = bd::align_up(sizeof(double) * (size_t)n, 256);
   size_t off = 0;
   L.fwd = off;
   off += step_layout(n, BD_PREC_FP64).total;
@@ -106,16 +108,11 @@ StepAdjointLayout step_adjoint_layout(int64_t n) {
   off += mat;
   L.cadj = off;
   off += bd::align_up(bd::cholesky_adjoint_workspace_bytes(n), 256);
-  L.z = off;
-  off += bd::align_up(sizeof(double) * n, 256);
-  L.xi = off;
-  off += bd::align_up(sizeof(double) * n, 256);
-  L.T = off;
-  off += bd::align_up(sizeof(double) * n, 256);
-  L.xnew = off;
-  off += bd::align_up(sizeof(double) * n, 256);
-  L.hpart = off;
-  off += bd::align_up(sizeof(double) * n, 256);
+  size_t* v[] = {&L.z, &L.xi, &L.T, &L.f, &L.dz, &L.xbd, &L.hpart, &L.hstep};
+  for (size_t* p : v) {
+    *p = off;
+    off += vec;
+  }
   L.total = off;
   return L;
 }
@@ -432,6 +429,76 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
                        s, d_x, xs, n, h->st);
     he = hipGetLastError();
   }
+  return hip_status(he);
+}
+
+bd_status_t bd_constrain_adjoint(bd_handle_t h, const bd_params_t* p, const double* d_x_old,
+                                 const double* d_x_new, const double* d_xbar, double* d_z,
+                                 void* d_ws, size_t ws_bytes) {
+  CallScope scope(h);
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!params_ok(p) || !d_x_old || !d_x_new || !d_xbar || !d_z || !d_ws) return BD_ERR_PARAM;
+  if (p->n_beads > bd::constrain_max_beads()) return BD_ERR_UNSUPPORTED;
+  if (ws_bytes < bd::constrain_workspace_bytes(p->n_beads)) return BD_ERR_PARAM;
+  if (reset(h) != hipSuccess) return BD_ERR_HIP;
+  return hip_status(bd::launch_constrain_adjoint(h->stream, *p, d_x_old, d_x_new, d_xbar, d_z,
+                                                 d_ws, h->st, h->host));
+}
+
+bd_status_t bd_step_adjoint(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_x,
+                            double* d_xbar, double* d_hbar, double* d_kbar, void* d_ws,
+                            size_t ws_bytes) {
+  CallScope scope(h);
+  bd_status_t e = enter(h);
+  if (e != BD_OK) return e;
+  if (!params_ok(p) || !d_x || !d_xbar || !d_hbar || !d_kbar || !d_ws) return BD_ERR_PARAM;
+  if (p->n_beads > bd::constrain_max_beads()) return BD_ERR_UNSUPPORTED;
+  const int64_t n = 3 * (int64_t)p->n_beads;
+  const StepAdjointLayout A = step_adjoint_layout(n);
+  if (ws_bytes < A.total) return BD_ERR_PARAM;
+  const StepLayout L = step_layout(n, BD_PREC_FP64);
+  char* base = static_cast<char*>(d_ws);
+  char* fwd = base + A.fwd;
+  double* D = reinterpret_cast<double*>(fwd + L.d);
+  double* y = reinterpret_cast<double*>(fwd + L.y);
+  double* xs = reinterpret_cast<double*>(fwd + L.xs);
+  auto vec = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
+  double *Lbar = vec(A.lbar), *Dbar = vec(A.dbar), *z = vec(A.z), *xi = vec(A.xi), *T = vec(A.T);
+  double *f = vec(A.f), *Dz = vec(A.dz), *xbD = vec(A.xbd), *hpart = vec(A.hpart);
+  double* hstep = vec(A.hstep);
+  const int64_t ld = step_ld(n);
+  hipStream_t s = h->stream;
+  // the forward step from x, recomputed (FP64): D, B, xi and y, x*, the
+  // tensions T and x^{t+dt} (in xs)
+  hipError_t he = reset(h);
+  if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
+  if (he == hipSuccess)
+    he = bd::launch_cholesky(s, h->aux, h->ev, n, D, ld, BD_PREC_FP64, fwd + L.chol, h->st,
+                              h->step_panels, h->wide_rows, h->tile_potrf);
+  if (he == hipSuccess) he = bd::launch_brownian(s, *p, step, D, ld, y, xi, fwd + L.brown);
+  if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);
+  if (he == hipSuccess)
+    he = bd::launch_constrain(s, *p, d_x, xs, T, fwd + L.cons, h->st, h->host, &h->pairs_hint);
+  // the tensions' adjoint: z, the gradient in x^{t+dt} at fixed T
+  if (he == hipSuccess)
+    he = bd::launch_constrain_adjoint(s, *p, d_x, xs, d_xbar, z, fwd + L.cons, h->st, h->host);
+  // x^{t+dt} = x* + dt D(x) f(T, u(x)): Dbar = dt z f^T, the gradient
+  // through u and through x* = x + dt kappa x + y (xbar overwritten)
+  if (he == hipSuccess) he = bd::launch_rod_forces(s, d_x, T, p->n_beads, f);
+  if (he == hipSuccess) he = bd::launch_rank1(s, z, f, p->dt, n, Dbar, ld);
+  if (he == hipSuccess) he = bd::launch_dmatvec(s, *p, d_x, z, Dz, nullptr);
+  if (he == hipSuccess)
+    he = bd::launch_step_adjoint_local(s, *p, d_x, T, z, Dz, d_xbar, d_kbar);
+  // y = c_B B xi: Lbar, then the factorisation's adjoint added into Dbar
+  if (he == hipSuccess) he = bd::launch_brownian_adjoint_lbar(s, *p, xi, z, Lbar, ld);
+  if (he == hipSuccess)
+    he = bd::launch_cholesky_adjoint(s, n, D, ld, 0, Lbar, ld, 0, Dbar, ld, 0, 1.0, 1.0, 1,
+                                     base + A.cadj);
+  // D(x, h*): the assembly's adjoint, then the sums
+  if (he == hipSuccess)
+    he = bd::launch_rpy_adjoint(s, *p, d_x, Dbar, ld, xbD, hstep, hpart, h->st);
+  if (he == hipSuccess) he = bd::launch_step_adjoint_finish(s, n, xbD, hstep, d_xbar, d_hbar);
   return hip_status(he);
 }
 

@@ -217,6 +217,16 @@ hipError_t launch_brownian_adjoint(hipStream_t s, const bd_params_t& p, const do
   return hipGetLastError();
 }
 
+hipError_t launch_brownian_adjoint_lbar(hipStream_t s, const bd_params_t& p, const double* xi,
+                                        const double* ybar, double* Lbar, int64_t ldb) {
+  const int64_t n = 3 * (int64_t)p.n_beads;
+  const double c = (p.noise == BD_NOISE_UNIFORM_PAPER) ? sqrt(6.0 * p.dt) : sqrt(2.0 * p.dt);
+  const int64_t nt = (n + kAdjTile - 1) / kAdjTile;
+  BD_LAUNCH("brownian_adjoint_l", brownian_adjoint_l_kernel, dim3((unsigned)(nt * (nt + 1) / 2)),
+            dim3(256), 0, s, xi, ybar, n, c, Lbar, ldb);
+  return hipGetLastError();
+}
+
 size_t brownian_workspace_bytes(int64_t n) {
   const int64_t nt = trmv_tiles(n);
   return align_up(sizeof(double) * n, 256) + align_up(sizeof(double) * nt * n, 256);

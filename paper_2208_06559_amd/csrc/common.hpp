@@ -56,6 +56,18 @@ hipError_t launch_cholesky_adjoint(hipStream_t s, int64_t n, const double* L, in
                                    double* Abar, int64_t lda, int64_t sAb, double alpha,
                                    double beta, int batch, void* ws);
 
+// The step adjoint's local parts (adjoint.hip): rod forces f(T, u(x)),
+// Dbar = dt z f^T (every element), the gradient through u, the predictor
+// and kappa (xbar overwritten, kbar accumulated), and the final sums.
+hipError_t launch_rod_forces(hipStream_t s, const double* x, const double* T, int N, double* f);
+hipError_t launch_rank1(hipStream_t s, const double* z, const double* f, double c, int64_t n,
+                        double* Dbar, int64_t ld);
+hipError_t launch_step_adjoint_local(hipStream_t s, const bd_params_t& p, const double* x,
+                                     const double* T, const double* z, const double* Dz,
+                                     double* xbar, double* kbar);
+hipError_t launch_step_adjoint_finish(hipStream_t s, int64_t n, const double* xbD,
+                                      const double* hstep, double* xbar, double* hbar);
+
 // brownian.hip
 size_t brownian_workspace_bytes(int64_t n);
 hipError_t launch_brownian(hipStream_t s, const bd_params_t& p, int64_t step, const double* L,
@@ -70,6 +82,9 @@ int64_t brownian_scratch_max_n();
 hipError_t launch_brownian_adjoint(hipStream_t s, const bd_params_t& p, const double* L,
                                    int64_t ld, const double* xi, const double* ybar,
                                    double* Lbar, int64_t ldb, double* xibar);
+// Only the L part of it: Lbar = c_B tril(ybar xi^T).
+hipError_t launch_brownian_adjoint_lbar(hipStream_t s, const bd_params_t& p, const double* xi,
+                                        const double* ybar, double* Lbar, int64_t ldb);
 
 // constrain.hip
 size_t constrain_workspace_bytes(int64_t n_beads);
@@ -77,7 +92,15 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
                             double* T_out, void* ws, DevState* st, DevState* host_state_pinned,
                             int* pairs_hint);
 
-// r = D(x) f, matrix-free (the tension solve's product); st->done must be 0.
+// Adjoint of the tension solve (bd_constrain_adjoint): z = xbar - 2 Delta^T
+// (Q mu) with J^T mu = -dt U^T Delta D(x_old) xbar; polls like
+// launch_constrain.  ws: constrain_workspace_bytes(N).
+hipError_t launch_constrain_adjoint(hipStream_t s, const bd_params_t& p, const double* x_old,
+                                    const double* x_new, const double* xbar, double* z, void* ws,
+                                    DevState* st, DevState* host_state);
+
+// r = D(x) f, matrix-free (the tension solve's product); returns at once
+// when st is given and st->done is set.
 hipError_t launch_dmatvec(hipStream_t s, const bd_params_t& p, const double* x, const double* f,
                           double* r, const DevState* st);
 

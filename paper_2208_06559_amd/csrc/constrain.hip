@@ -32,7 +32,7 @@ constexpr int kCtlThreads = 512;   // controller workgroup
 constexpr int kMaxRods = 4096;     // LDS capacity of the tridiagonal solve
 constexpr int kMvI = 16;           // beads i per matvec workgroup
 
-enum { PH_RESID = 0, PH_KRYLOV = 1 };
+enum { PH_RESID = 0, PH_KRYLOV = 1, PH_ADJ_RHS = 2 };
 
 struct NewtonCtl {
   int32_t phase;
@@ -264,7 +264,7 @@ __device__ __forceinline__ void dmatvec_body(int bx, const double* __restrict__ 
                                              const double* __restrict__ f, double* __restrict__ r,
                                              int N, const RpyConst& kc,
                                              const DevState* __restrict__ st) {
-  if (st->done) return;
+  if (st && st->done) return;  // st null: always run
   __shared__ double sx[3 * kChunk], sf[3 * kChunk];
   __shared__ double red[kMvWaves][3][kMvI];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -493,9 +493,17 @@ __device__ void rod_forces(const double* z, const double* __restrict__ u,
 // triangular solve) in LDS and each thread's share of the Krylov vector in
 // registers (unknowns k = tid + kCtlThreads q): global memory is touched only
 // by batches of independent loads and by the stores of the next state.
+//
+// kAdj: the same Krylov machinery solves the adjoint system of the tension
+// solve, J^T mu = -dt U^T Delta D xbar (see launch_constrain_adjoint): J^T
+// is J with the roles of the rod directions u (forces) and the new rod
+// vectors Q (contraction) exchanged, the band arrays hold tri(J^T), and the
+// first product is D xbar.  xs then receives z = xbar - 2 Delta^T (Q mu).
+template <bool kAdj>
 __device__ __forceinline__ void newton_controller_body(
     Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, double dt,
-    double bl, double tol, int maxit, DevState* __restrict__ st) {
+    double bl, double tol, int maxit, DevState* __restrict__ st,
+    const double* __restrict__ xbar = nullptr) {
   __shared__ double pa[kPadRods], pb[kPadRods], pc[kPadRods], pd[kPadRods];
   __shared__ double red[kCtlThreads / 64];
   __shared__ double red8[kCtlThreads / 64][8];
@@ -511,7 +519,58 @@ __device__ __forceinline__ void newton_controller_body(
   const int phase = ctl->phase, j = ctl->j, newton_it = ctl->newton_it;
   const double beta_c = ctl->beta, eta = ctl->eta;
   if (done) return;
-  if (phase == PH_RESID) {
+  if (kAdj && phase == PH_ADJ_RHS) {
+    // rhs = -dt U^T Delta (D xbar), with r = D xbar from the first product
+    double g2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      const int k = tid + q * kCtlThreads;
+      const int kc = (k < M) ? k : M - 1;
+      double v = 0.0;
+#pragma unroll
+      for (int al = 0; al < 3; ++al)
+        v += b.u[3 * kc + al] * (b.r[3 * (kc + 1) + al] - b.r[3 * kc + al]);
+      const double lo = b.lo[kc], di = b.di[kc], up = b.up[kc];
+      if (k < M) {
+        const double rhs = -dt * v;
+        pd[lp(k)] = rhs;
+        g2 += rhs * rhs;
+        pa[lp(k)] = lo;
+        pb[lp(k)] = di;
+        pc[lp(k)] = up;
+      }
+    }
+    const double beta = sqrt(block_sum(g2, red));
+    if (!(beta > 0.0)) {  // mu = 0 (or a non-finite right side)
+      for (int64_t e = tid; e < n3; e += kCtlThreads) xs[e] = xbar[e];
+      if (tid == 0) {
+        if (st->status == BD_OK && !(beta == 0.0)) st->status = BD_ERR_NO_CONVERGE;
+        st->done = 1;
+      }
+      return;
+    }
+    const double rb = 1.0 / beta;
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+      const int k = tid + q * kCtlThreads;
+      if (k < M) {
+        const double v0 = pd[lp(k)] * rb;
+        b.V[k] = v0;
+        pd[lp(k)] = v0;
+      }
+    }
+    if (tid == 0) {
+      b.s[0] = beta;
+      ctl->phase = PH_KRYLOV;
+      ctl->j = 0;
+      ctl->beta = beta;
+      ctl->eta = tol;
+    }
+    cr_solve(M, pa, pb, pc, pd);
+    rod_forces(pd, b.Q, b.f, N);
+    return;
+  }
+  if (!kAdj && phase == PH_RESID) {
     double err = 0.0, res = 0.0, g2 = 0.0;
 #pragma unroll
     for (int q = 0; q < kR; ++q) {
@@ -607,7 +666,7 @@ __device__ __forceinline__ void newton_controller_body(
   for (int q = 0; q < kR; ++q) {
     const int k = tid + q * kCtlThreads;
     const int kc = (k < M) ? k : M - 1;  // valid index: loads issue together
-    const double* qk = b.Q + 3 * kc;
+    const double* qk = (kAdj ? b.u : b.Q) + 3 * kc;
     const double d0 = b.r[3 * (kc + 1)] - b.r[3 * kc];
     const double d1 = b.r[3 * (kc + 1) + 1] - b.r[3 * kc + 1];
     const double d2 = b.r[3 * (kc + 1) + 2] - b.r[3 * kc + 2];
@@ -784,6 +843,26 @@ __device__ __forceinline__ void newton_controller_body(
       told[q] = b.T[(k < M) ? k : M - 1];
     }
     cr_solve(M, pa, pb, pc, pd);
+    if constexpr (kAdj) {
+      // mu = P^-1 (V y) is in pd: z_i = xbar_i - 2 (Q_{i-1} mu_{i-1} - Q_i mu_i)
+      for (int i = tid; i < N; i += kCtlThreads) {
+        const double mm = (i > 0) ? pd[lp(i - 1)] : 0.0, mi = (i < M) ? pd[lp(i)] : 0.0;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+          const double qm = (i > 0) ? b.Q[3 * (i - 1) + al] : 0.0;
+          const double qi = (i < M) ? b.Q[3 * i + al] : 0.0;
+          xs[3 * i + al] = xbar[3 * i + al] - 2.0 * (qm * mm - qi * mi);
+        }
+      }
+      if (tid == 0) {
+        const bool ok = fabs(s_s[j + 1]) <= eta * beta;
+        if (st->status == BD_OK && !ok) st->status = BD_ERR_NO_CONVERGE;
+        st->krylov_iters = ctl->kry;
+        st->last_newton_res = fabs(s_s[j + 1]) / beta;
+        st->done = 1;
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < kR; ++q) {
       const int k = tid + q * kCtlThreads;
@@ -806,7 +885,7 @@ __device__ __forceinline__ void newton_controller_body(
       if (k < M) pd[lp(k)] = wv[q];
     }
     cr_solve(M, pa, pb, pc, pd);
-    rod_forces(pd, b.u, b.f, N);
+    rod_forces(pd, kAdj ? b.Q : b.u, b.f, N);
     if (tid == 0) ctl->j = j + 1;
   }
 }
@@ -814,7 +893,63 @@ __device__ __forceinline__ void newton_controller_body(
 __global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
     Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, double dt,
     double bl, double tol, int maxit, DevState* __restrict__ st) {
-  newton_controller_body(b, xs, T_out, N, dt, bl, tol, maxit, st);
+  newton_controller_body<false>(b, xs, T_out, N, dt, bl, tol, maxit, st);
+}
+
+// Adjoint of the tension solve: rod directions u at x_old, the new rod
+// vectors Q at x_new, the transposed band of the Jacobian at Q,
+// (J^T)_{k,k-1} = J_{k-1,k} = -2 dt Q_{k-1} . G_{k-1,k} u_k,
+// (J^T)_kk = -2 dt Q_k . G_kk u_k, (J^T)_{k,k+1} = -2 dt Q_{k+1} . G_{k+1,k} u_k,
+// and f = xbar for the first product (r = D xbar).
+__global__ __launch_bounds__(256) void constrain_adjoint_init_kernel(
+    const double* __restrict__ x_old, const double* __restrict__ x_new,
+    const double* __restrict__ xbar, Bufs b, int N, double hstar, double a, double dt,
+    DevState* st) {
+  const int M = N - 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < M) {
+    const int k = t;
+    double u[3], qk[3], o[3];
+    unit_bond(x_old, k, u);
+    for (int al = 0; al < 3; ++al) {
+      qk[al] = x_new[3 * (k + 1) + al] - x_new[3 * k + al];
+      b.u[3 * k + al] = u[al];
+      b.Q[3 * k + al] = qk[al];
+    }
+    g_apply(x_old, k, k, hstar, a, u, o);
+    b.di[k] = -2.0 * dt * (qk[0] * o[0] + qk[1] * o[1] + qk[2] * o[2]);
+    double lo = 0.0, up = 0.0;
+    if (k > 0) {
+      double qm[3];
+      for (int al = 0; al < 3; ++al) qm[al] = x_new[3 * k + al] - x_new[3 * (k - 1) + al];
+      g_apply(x_old, k - 1, k, hstar, a, u, o);
+      lo = -2.0 * dt * (qm[0] * o[0] + qm[1] * o[1] + qm[2] * o[2]);
+    }
+    if (k + 1 < M) {
+      double qp[3];
+      for (int al = 0; al < 3; ++al) qp[al] = x_new[3 * (k + 2) + al] - x_new[3 * (k + 1) + al];
+      g_apply(x_old, k + 1, k, hstar, a, u, o);
+      up = -2.0 * dt * (qp[0] * o[0] + qp[1] * o[1] + qp[2] * o[2]);
+    }
+    b.lo[k] = lo;
+    b.up[k] = up;
+  }
+  for (int64_t e = t; e < 3 * (int64_t)N; e += (int64_t)gridDim.x * blockDim.x) b.f[e] = xbar[e];
+  if (t == 0) {
+    b.ctl->phase = PH_ADJ_RHS;
+    b.ctl->j = 0;
+    b.ctl->newton_it = 0;
+    b.ctl->kry = 0;
+    b.ctl->beta = 0.0;
+    b.ctl->eta = 0.0;
+    st->done = 0;
+  }
+}
+
+__global__ __launch_bounds__(kCtlThreads) void adjoint_controller_kernel(
+    Bufs b, const double* __restrict__ xbar, double* __restrict__ z, int N, double dt, double tol,
+    DevState* __restrict__ st) {
+  newton_controller_body<true>(b, z, nullptr, N, dt, 1.0, tol, 0, st, xbar);
 }
 
 // Ensembles: chain blockIdx.z of the table, its workspace carved in place;
@@ -838,7 +973,8 @@ __global__ __launch_bounds__(kMvThreads) void dmatvec_batched_kernel(
 __global__ __launch_bounds__(kCtlThreads) void newton_controller_batched_kernel(
     const ChainDesc* __restrict__ cd) {
   const ChainDesc& c = cd[blockIdx.z];
-  newton_controller_body(carve(c.cons, c.N), c.xs, nullptr, c.N, c.dt, c.b, c.tol, c.maxit, c.st);
+  newton_controller_body<false>(carve(c.cons, c.N), c.xs, nullptr, c.N, c.dt, c.b, c.tol, c.maxit,
+                                c.st);
 }
 
 // States of `count` chains whose iteration the host stopped launching:
@@ -902,6 +1038,43 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
   } else if (pairs_hint) {
     *pairs_hint = host_state->newton_iters + host_state->krylov_iters;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_constrain_adjoint(hipStream_t s, const bd_params_t& p, const double* x_old,
+                                    const double* x_new, const double* xbar, double* z, void* ws,
+                                    DevState* st, DevState* host_state) {
+  const int N = p.n_beads;
+  const int M = N - 1;
+  Bufs b = carve(ws, N);
+  int iblk = (M + 255) / 256;
+  if (iblk < 16) iblk = 16;
+  BD_LAUNCH("constrain_adjoint_init", constrain_adjoint_init_kernel, dim3(iblk), dim3(256), 0, s,
+            x_old, x_new, xbar, b, N, p.hstar, p.a, p.dt, st);
+  const dim3 mvgrid((N + kMvI - 1) / kMvI);
+  const RpyConst kc = rpy_const(p.hstar, p.a);
+  // (matvec, controller) pairs: the first gives D xbar and the right side,
+  // each further one a Krylov step; the host polls as for the forward solve
+  const int cap = kKmax + 2;
+  int batch = 16, launched = 0;
+  while (launched < cap) {
+    if (batch > cap - launched) batch = cap - launched;
+    for (int c = 0; c < batch; ++c) {
+      BD_LAUNCH("dmatvec", dmatvec_kernel, mvgrid, dim3(kMvThreads), 0, s, x_old, b.f, b.r, N, kc,
+                st);
+      BD_LAUNCH("adjoint_controller", adjoint_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s,
+                b, xbar, z, N, p.dt, p.newton_tol, st);
+    }
+    launched += batch;
+    hipError_t e = hipMemcpyAsync(host_state, st, sizeof(DevState), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (host_state->done) break;
+    batch = 8;
+  }
+  if (!host_state->done)
+    BD_LAUNCH("constrain_unfinished", constrain_unfinished_kernel, dim3(1), dim3(64), 0, s, st, 1);
   return hipGetLastError();
 }
 

@@ -1,4 +1,5 @@
 // Runs the whole rigid-rod tension solve of constrain.hip (launch_constrain:
+// then its adjoint, launch_constrain_adjoint;
 // the host's batches of matrix-free products and controller passes) on the
 // CPU through the stand-in HIP runtime, under AddressSanitizer, with every
 // buffer at exactly the documented size.  Values are meaningless there (no
@@ -42,11 +43,19 @@ int main(int argc, char** argv) {
   const hipError_t e = bd::launch_constrain(nullptr, p, x, xs, T, ws, st, host, &hint);
   printf("N=%d maxit=%d: status %d, %ld launches, done %d\n", N, maxit, e, g_emu_launches,
          host->done);
+  // the adjoint solve on the same workspace: exact-size xbar and z
+  double* xbar = (double*)malloc(sizeof(double) * 3 * N);
+  double* z = (double*)malloc(sizeof(double) * 3 * N);
+  for (int i = 0; i < 3 * N; ++i) xbar[i] = 1.0 + 0.1 * (i % 7);
+  const hipError_t ea = bd::launch_constrain_adjoint(nullptr, p, x, xs, xbar, z, ws, st, host);
+  printf("adjoint: status %d, %ld launches, done %d\n", ea, g_emu_launches, host->done);
+  free(xbar);
+  free(z);
   free(x);
   free(xs);
   free(T);
   free(ws);
   free(st);
   free(host);
-  return e;
+  return e | ea;
 }

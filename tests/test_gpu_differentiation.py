@@ -79,3 +79,51 @@ def test_cholesky_adjoint_of_gpu_factor_half_norm(h):
     M = B.matrix_view(Ab, n)
     err = (M - 0.5 * torch.eye(n, dtype=torch.float64, device=DEV)).abs().max().item()
     assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("N,hstar", [(2, 0.25), (7, 0.0), (40, 0.25), (300, 0.5), (1025, 0.25)])
+def test_constrain_adjoint_vs_oracle(h, N, hstar):
+    pg = B.make_params(N, hstar=hstar, dt=1e-3)
+    po = o.make_params(N, hstar=hstar, dt=1e-3)
+    rng = np.random.default_rng(N)
+    x = I.random_walk(N, seed=N + 7)
+    xs = x + 0.03 * rng.normal(size=x.shape)
+    xnew_o, _, info = o.constrain(po, x, xs)
+    assert info["status"] == o.OK
+    xbar = rng.normal(size=x.shape)
+    zref = o.constrain_adjoint(po, x, xnew_o, xbar)
+    xg = _dev(xs)
+    h.constrain(pg, _dev(x), xg)
+    assert h.info()["status"] == B.OK
+    z = torch.full((N, 3), float("nan"), dtype=torch.float64, device=DEV)
+    h.constrain_adjoint(pg, _dev(x), xg, _dev(xbar), z)
+    st = h.info()
+    assert st["status"] == B.OK, st
+    np.testing.assert_allclose(z.cpu().numpy(), zref, rtol=0, atol=1e-9 * np.abs(zref).max())
+
+
+STEP_CASES = [(2, 0.25, "none", 0, 1e-3), (5, 0.25, "planar", 0, 1e-3),
+              (32, 0.25, "none", 0, 1e-4), (64, 0.0, "shear", 0, 1e-4),
+              (100, 0.25, "uniaxial", 1, 1e-4), (256, 0.25, "planar", 0, 1e-4)]
+
+
+@pytest.mark.parametrize("N,hstar,flow,noise,dt", STEP_CASES)
+def test_step_adjoint_vs_oracle(h, N, hstar, flow, noise, dt):
+    kap = I.kappa_for(flow, 20.0) if flow != "none" else np.zeros((3, 3))
+    kw = dict(dt=dt, hstar=hstar, kappa=kap, seed=5, chain_id=N, noise=noise)
+    pg, po = B.make_params(N, **kw), o.make_params(N, **kw)
+    x = I.random_walk(N, seed=5, chain=N)
+    rng = np.random.default_rng(N + 3)
+    xbar_next = rng.normal(size=(N, 3))
+    xb_ref, hb_ref, kb_ref = o.step_adjoint(po, 3, x, xbar_next)
+    xbar = _dev(xbar_next)
+    hbar = torch.full((1,), 0.5, dtype=torch.float64, device=DEV)  # accumulated into
+    kbar = torch.full((9,), -0.25, dtype=torch.float64, device=DEV)
+    h.step_adjoint(pg, 3, _dev(x), xbar, hbar, kbar)
+    st = h.info()
+    assert st["status"] == B.OK, st
+    np.testing.assert_allclose(xbar.cpu().numpy(), xb_ref, rtol=0,
+                               atol=1e-9 * np.abs(xb_ref).max())
+    np.testing.assert_allclose(hbar.item() - 0.5, hb_ref, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(kbar.cpu().numpy().reshape(3, 3) + 0.25, kb_ref, rtol=0,
+                               atol=1e-9 * max(1e-12, np.abs(kb_ref).max()))
