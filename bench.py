@@ -124,7 +124,8 @@ def syrk_per_launch(n: int, esize: int, kind: str = "bulk") -> tuple[float, floa
 
 
 COPY_PROBE_BYTES = 1 << 30
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "syrk_update_f32_n12288_traffic.md")
+PROFILES = os.path.join(ROOT, "profiles")
+MFMA_RECORD = os.path.join(PROFILES, "cholesky_mfma_counters_n12288.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2208_06559_amd", "csrc", "cholesky.hip")
 
 
@@ -140,23 +141,111 @@ def copy_probe(torch) -> int:
     return 0
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when there is none or the kernel source changed since."""
+def _records(prefix: str, paths):
+    """The JSON records after `prefix` in the committed summaries whose
+    kernel source still has the hash they were measured with."""
     import hashlib
     try:
-        rec = None
-        with open(TRAFFIC_RECORD) as f:
-            for line in f:
-                if line.startswith("traffic_record: "):
-                    rec = json.loads(line[len("traffic_record: "):])
         with open(KERNEL_SOURCE, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, ValueError):
-        return None
-    if not rec or rec.get("kernel") != kernel or rec.get("source_sha256") != sha:
-        return None
-    return float(rec["hbm_bytes_per_launch"])
+    except OSError:
+        return []
+    out = []
+    for path in paths:
+        try:
+            with open(path) as f:
+                for line in f:
+                    if line.startswith(prefix):
+                        rec = json.loads(line[len(prefix):])
+                        if rec.get("source_sha256") == sha:
+                            out.append(rec)
+        except (OSError, ValueError):
+            continue
+    return out
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summaries
+    (profiles/*_traffic.md), or None when there is none or the kernel source
+    changed since."""
+    import glob
+    for rec in _records("traffic_record: ", sorted(glob.glob(os.path.join(PROFILES, "*_traffic.md")))):
+        if rec.get("kernel") == kernel:
+            return float(rec["hbm_bytes_per_launch"])
+    return None
+
+
+def measured_mfma(kernel: str):
+    """Matrix-core counters of `kernel` (syrk_update_f32 / _f64) from the
+    committed summary, or None."""
+    name = {"syrk_update_f32": "syrk_update_kernel<float, 128>",
+            "syrk_update_f64": "syrk_update_kernel<double, 128>"}.get(kernel)
+    for rec in _records("mfma_record: ", [MFMA_RECORD]):
+        k = rec.get("kernels", {}).get(name)
+        if k:
+            return {"mfma_busy_frac": k["mfma_busy_frac"],
+                    "mfma_flops_per_dispatch": k["mfma_flops_per_dispatch"],
+                    "source": "profiles/cholesky_mfma_counters_n12288.md"}
+    return None
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def error_series(B, torch, np, h, p, x0, n, w, args) -> dict:
+    """Mixed-precision error along the workload's trajectory: the mixed and
+    FP64 steps run side by side from the same start and noise for
+    `series_steps` steps; after every step the largest bead-position
+    difference in units of b, and every `series_every` steps (and at the
+    start) the relative residual ||B B^T - D||_F / ||D||_F of the mixed
+    factor of D at the mixed trajectory's configuration, the product formed
+    by an FP64 GEMM (validation only)."""
+    xm, xd = x0.clone(), x0.clone()
+    wsm = h.workspace(B.OP_STEP, n, B.PREC_MIXED)
+    wsd = h.workspace(B.OP_STEP, n, B.PREC_FP64)
+    wsc = h.workspace(B.OP_CHOLESKY, n, B.PREC_MIXED)
+    D = torch.empty((n, n), dtype=torch.float64, device=x0.device)
+    pos, res_steps, res = [], [], []
+
+    def residual(x):
+        h.rpy_assemble(p, x, D, n, B.FILL_FULL)
+        Dm = B.matrix_view(D, n).clone()
+        h.cholesky(D, n, n, B.PREC_MIXED, wsc)
+        if h.info()["status"] != B.OK:
+            raise RuntimeError("series: mixed factorisation failed")
+        L = torch.tril(B.matrix_view(D, n))
+        r = (torch.linalg.norm(L @ L.T - Dm) / torch.linalg.norm(Dm)).item()
+        del L, Dm
+        return r
+
+    for s in range(args.series_steps):
+        if s % args.series_every == 0:
+            res_steps.append(s)
+            res.append(residual(xm))
+        h.step(p, s, xm, B.PREC_MIXED, wsm)
+        h.step(p, s, xd, B.PREC_FP64, wsd)
+        st = h.info()
+        if st["status"] != B.OK:
+            raise RuntimeError(f"series step {s}: {st}")
+        pos.append(((xm - xd).abs().max() / w.b).item())
+    res_steps.append(args.series_steps)
+    res.append(residual(xm))
+    del D
+    torch.cuda.empty_cache()
+    out = {"steps": args.series_steps, "position_error_per_step": pos,
+           "position_error_max": max(pos), "residual_steps": res_steps,
+           "residual_mixed": res, "residual_mixed_max": max(res)}
+    log(f"series: position error max {out['position_error_max']:.3e} b, "
+        f"residual max {out['residual_mixed_max']:.3e}")
+    return out
 
 
 def ensemble_leg(B, I, torch, np, precs, args, dev) -> dict:
@@ -278,6 +367,12 @@ def main() -> int:
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--cpu-beads", type=int, default=4096,
                     help="chain length of the CPU oracle sample (scaled to N=4096 by n^3)")
+    ap.add_argument("--cpu-beads-single", type=int, default=1024,
+                    help="chain length of the single-thread oracle sample (scaled by n^3)")
+    ap.add_argument("--series-steps", type=int, default=200,
+                    help="steps of the mixed-vs-FP64 error series (0: skip it)")
+    ap.add_argument("--series-every", type=int, default=20,
+                    help="residual of the mixed factor every this many steps of the series")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=20,
                     help="timed steps of the 256-chain ensemble leg (0: skip it)")
@@ -448,6 +543,8 @@ def main() -> int:
                 achieved, peak, unit, bound = fl / avg_s / 1e12, peak_fl, "TFLOP/s", "mfma"
             rf = {"bound": bound, "kernel": kern, "achieved": achieved, "peak": peak,
                   "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(kern),
+                  "mfma_counters": measured_mfma(kern),
+                  "cholesky_frac_of_peak": result[prec_name].get("cholesky_frac_of_peak"),
                   "algorithmic_flops_per_launch": fl, "algorithmic_bytes_per_launch": by,
                   "intensity_flop_per_byte": fl / by,
                   "tflops_per_launch_avg": fl / avg_s / 1e12,
@@ -502,13 +599,31 @@ def main() -> int:
         _, io = o.step(po, 0, xs0)
         dt_s = time.perf_counter() - t0
         scale = (Ns / N) ** 3
-        cpu = {"value": scale / dt_s, "unit": "steps/s", "cores": o.num_threads(), "kind": "oracle",
+        threads = o.num_threads()
+        # one thread, on a shorter piece of the same chain (the unblocked
+        # factorisation, n^3/3 flop, dominates the oracle's step)
+        N1 = min(args.cpu_beads_single, N)
+        o.set_num_threads(1)
+        t0 = time.perf_counter()
+        _, io1 = o.step(o.make_params(N1, **kw), 0, x0_np[:N1].copy())
+        dt_1 = time.perf_counter() - t0
+        o.set_num_threads(threads)
+        s1 = (N1 / N) ** 3
+        cpu = {"value": scale / dt_s, "unit": "steps/s", "cores": threads, "kind": "oracle",
                "sample": f"1 oracle FP64 step of the same chain truncated to N={Ns} "
-                         f"(n={3 * Ns}), {dt_s:.2f} s measured, scaled by (n_s/n)^3 = "
-                         f"{scale:.4g} to n={n}",
-               "measured_s_per_step": dt_s, "status": io["status"]}
+                         f"(n={3 * Ns}), {dt_s:.2f} s measured on {threads} threads, scaled by "
+                         f"(n_s/n)^3 = {scale:.4g} to n={n}",
+               "measured_s_per_step": dt_s, "status": io["status"],
+               "cpu_model": cpu_model(),
+               "single_thread": {"value": s1 / dt_1, "unit": "steps/s", "cores": 1,
+                                 "sample": f"1 oracle FP64 step of the chain truncated to N={N1} "
+                                           f"(n={3 * N1}), {dt_1:.2f} s on 1 thread, scaled "
+                                           f"by (n_s/n)^3 = {s1:.4g} to n={n}",
+                                 "measured_s_per_step": dt_1, "status": io1["status"]}}
         log(f"cpu oracle: {cpu}")
 
+    series = (error_series(B, torch, np, h, p, x0, n, w, args)
+              if args.series_steps > 0 and len(precs) == 2 else None)
     ens = ensemble_leg(B, I, torch, np, precs, args, dev) if args.ensemble_steps > 0 else None
     fraenkel = fraenkel_leg(B, torch, h, p, x0, n, w, precs, args) if args.fraenkel_steps > 0 else None
 
@@ -539,6 +654,7 @@ def main() -> int:
         "kernel_breakdown": breakdown,
         "other_precision_profile": other,
         "cpu_baseline": cpu,
+        "mixed_error_series": series,
         "ensemble": ens,
         "fraenkel": fraenkel,
         "context": extra,

@@ -699,3 +699,8 @@ int bdo_run_many(const bdo_params* p, int32_t nchains, const uint64_t* chain_ids
 }
 
 int bdo_num_threads(void) { return omp_get_max_threads(); }
+
+/* Threads of the oracle's parallel loops from now on (timing only). */
+void bdo_set_num_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}

@@ -122,6 +122,7 @@ int bdo_run_many(const bdo_params* p, int32_t nchains, const uint64_t* chain_ids
 
 /* OpenMP threads the oracle's parallel loops use. */
 int bdo_num_threads(void);
+void bdo_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

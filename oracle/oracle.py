@@ -110,6 +110,8 @@ def lib():
         L.bdo_run_many.restype = C.c_int
         L.bdo_num_threads.argtypes = []
         L.bdo_num_threads.restype = C.c_int
+        L.bdo_set_num_threads.argtypes = [C.c_int]
+        L.bdo_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -497,3 +499,8 @@ def run_many(p: Params, chain_ids, step0: int, nsteps: int, X: np.ndarray):
 
 def num_threads() -> int:
     return int(lib().bdo_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    lib().bdo_set_num_threads(int(n))
