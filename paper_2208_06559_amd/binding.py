@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -188,9 +189,12 @@ class Handle:
         _check(lib().bd_create(C.byref(h), dev, C.c_void_p(stream)), "bd_create")
         self._h = h
         self._ws = {}
+        self._ensembles = weakref.WeakSet()  # destroyed before the handle
 
     def close(self):
         if self._h:
+            for e in list(self._ensembles):
+                e.close()
             lib().bd_destroy(self._h)
             self._h = None
 
@@ -414,6 +418,7 @@ class Ensemble:
                                         _dev_f64(x, "x", n_tot), self.ws.data_ptr(), nbytes,
                                         C.byref(e)), "bd_ensemble_create")
         self._e = e
+        handle._ensembles.add(self)
 
     def step(self, step: int):
         self.handle._sync_stream()
@@ -426,7 +431,8 @@ class Ensemble:
 
     def close(self):
         if self._e:
-            lib().bd_ensemble_destroy(self._e)
+            if self.handle._h:  # the handle's close() destroys its ensembles first
+                lib().bd_ensemble_destroy(self._e)
             self._e = None
 
     def __del__(self):

@@ -34,6 +34,7 @@ struct bd_handle_s {
   int64_t wide_rows;   // steps of more than two panels while more rows than this remain
   bool tile_potrf;     // Cholesky diagonal blocks on matrix cores
   void* scratch;       // this device's fixed scratch array (bd_brownian_noalloc)
+  int ps_cu;           // workgroups of the one-launch tension solve (0: host-polled launches)
 };
 
 namespace {
@@ -235,6 +236,12 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   h->aux = nullptr;
   h->ev[0] = h->ev[1] = h->ev[2] = h->ev[3] = nullptr;
   h->scratch = nullptr;
+  // The tension solve alternates launches of the product with D and the
+  // controller, polled by the host; BDRPY_CONSTRAIN=onelaunch runs it as one
+  // launch of at most one workgroup per compute unit instead (no host round
+  // trip, so that a step can be captured in a HIP graph; slower).
+  const char* cm = getenv("BDRPY_CONSTRAIN");
+  h->ps_cu = (cm && cm[0] == 'o') ? prop.multiProcessorCount : 0;
   // BDRPY_STEP_PANELS=1 or 2 caps the panels per trailing pass (for
   // comparisons).  By default four panels share each pass while the
   // trailing matrix is large (more than BDRPY_WIDE_ROWS rows, default 4096),
@@ -394,7 +401,7 @@ bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_
   if (ws_bytes < bd::constrain_workspace_bytes(p->n_beads)) return BD_ERR_PARAM;
   if (reset(h) != hipSuccess) return BD_ERR_HIP;
   return hip_status(bd::launch_constrain(h->stream, *p, d_x_old, d_x_pred_inout, d_T_out, d_ws,
-                                         h->st, h->host, &h->pairs_hint));
+                                         h->st, h->host, &h->pairs_hint, h->ps_cu));
 }
 
 bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d_x,
@@ -423,7 +430,7 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);
   if (he == hipSuccess)
     he = bd::launch_constrain(s, *p, d_x, xs, nullptr, base + L.cons, h->st, h->host,
-                               &h->pairs_hint);
+                               &h->pairs_hint, h->ps_cu);
   if (he == hipSuccess) {
     BD_LAUNCH("commit_positions", commit_positions_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                        s, d_x, xs, n, h->st);
@@ -479,7 +486,8 @@ bd_status_t bd_step_adjoint(bd_handle_t h, const bd_params_t* p, int64_t step, c
   if (he == hipSuccess) he = bd::launch_brownian(s, *p, step, D, ld, y, xi, fwd + L.brown);
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);
   if (he == hipSuccess)
-    he = bd::launch_constrain(s, *p, d_x, xs, T, fwd + L.cons, h->st, h->host, &h->pairs_hint);
+    he = bd::launch_constrain(s, *p, d_x, xs, T, fwd + L.cons, h->st, h->host, &h->pairs_hint,
+                              h->ps_cu);
   // the tensions' adjoint: z, the gradient in x^{t+dt} at fixed T
   if (he == hipSuccess)
     he = bd::launch_constrain_adjoint(s, *p, d_x, xs, d_xbar, z, fwd + L.cons, h->st, h->host);

@@ -88,9 +88,12 @@ hipError_t launch_brownian_adjoint_lbar(hipStream_t s, const bd_params_t& p, con
 
 // constrain.hip
 size_t constrain_workspace_bytes(int64_t n_beads);
+// n_cu > 0: the whole solve in one launch of at most n_cu workgroups (no
+// host round trip, capturable); n_cu = 0: alternating launches polled by
+// the host.
 hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x_old, double* xs,
                             double* T_out, void* ws, DevState* st, DevState* host_state_pinned,
-                            int* pairs_hint);
+                            int* pairs_hint, int n_cu);
 
 // Adjoint of the tension solve (bd_constrain_adjoint): z = xbar - 2 Delta^T
 // (Q mu) with J^T mu = -dt U^T Delta D(x_old) xbar; polls like

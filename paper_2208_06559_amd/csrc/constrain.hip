@@ -43,9 +43,16 @@ struct NewtonCtl {
   double eta;
 };
 
+// Grid barrier of the one-launch solve: arrival counter, generation and an
+// abort flag (a workgroup that waited too long).
+struct GridBar {
+  uint32_t count, gen, abort, pad;
+};
+
 struct Bufs {
   double *u, *Qs, *Q, *Gd, *Gp, *Gm, *T, *lo, *di, *up, *f, *r, *V, *H, *cs, *sn, *s;
   NewtonCtl* ctl;
+  GridBar* gb;
 };
 
 
@@ -76,12 +83,13 @@ __host__ __device__ Bufs carve(void* ws, int N) {
   b.sn = take(kKmax);
   b.s = take(kKmax + 1);
   b.ctl = reinterpret_cast<NewtonCtl*>(take(8));
+  b.gb = reinterpret_cast<GridBar*>(take(2));
   return b;
 }
 
 size_t carve_bytes(int N) {
   Bufs b = carve(nullptr, N);
-  return reinterpret_cast<size_t>(b.ctl) + 256;
+  return reinterpret_cast<size_t>(b.gb) + 256;
 }
 
 // RPY coefficients (Eqs. 8-9) for the matrix-free products, without
@@ -209,6 +217,8 @@ __device__ __forceinline__ void constrain_init_body(int bx, const double* __rest
     b.ctl->kry = 0;
     b.ctl->beta = 0.0;
     b.ctl->eta = 0.0;
+    b.gb->count = 0;
+    b.gb->abort = 0;
     st->done = 0;
   }
 }
@@ -259,79 +269,99 @@ constexpr int kMvWaves = kMvThreads / 64;
 
 // kChunk: beads j staged in LDS per round (2048: 96 KB, one workgroup per
 // CU; 1024: two workgroups per CU, for the ensembles' shorter chains).
-template <int kChunk>
+// kThreads: 1024, or 512 where each wave also does the work of the wave
+// eight places on (the two sets of phases kept in separate accumulators,
+// so every sum is formed in the same order as with 1024 threads).  LDS:
+// sx, sf (3 kChunk each) and red (kMvWaves x 3 x kMvI), from the caller.
+constexpr int kMvLds = 3 * kMvWaves * kMvI;
+
+template <int kChunk, int kThreads>
 __device__ __forceinline__ void dmatvec_body(int bx, const double* __restrict__ x,
                                              const double* __restrict__ f, double* __restrict__ r,
                                              int N, const RpyConst& kc,
-                                             const DevState* __restrict__ st) {
+                                             const DevState* __restrict__ st, double* sx,
+                                             double* sf, double* redp) {
+  static_assert(kThreads == 1024 || kThreads == 512, "one or two phase sets per wave");
+  constexpr int kV = kMvThreads / kThreads;  // phase sets per wave
+  constexpr int kW = kThreads / 64;          // waves
   if (st && st->done) return;  // st null: always run
-  __shared__ double sx[3 * kChunk], sf[3 * kChunk];
-  __shared__ double red[kMvWaves][3][kMvI];
+  double(*red)[3][kMvI] = reinterpret_cast<double(*)[3][kMvI]>(redp);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int il = lane & 15, jp = lane >> 4;
   const int i = bx * kMvI + il;
   const int ii = (i < N) ? i : N - 1;
   const double xi0 = x[3 * ii], xi1 = x[3 * ii + 1], xi2 = x[3 * ii + 2];
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  double a0[kV], a1[kV], a2[kV];
+#pragma unroll
+  for (int v = 0; v < kV; ++v) a0[v] = a1[v] = a2[v] = 0.0;
   for (int j0 = 0; j0 < N; j0 += kChunk) {
     const int nj = (N - j0 < kChunk) ? N - j0 : kChunk;
     __syncthreads();
-    for (int e = tid; e < 3 * nj; e += kMvThreads) {
+    for (int e = tid; e < 3 * nj; e += kThreads) {
       sx[e] = x[3 * j0 + e];
       sf[e] = f[3 * j0 + e];
     }
     __syncthreads();
-    for (int jj = 4 * w + jp; jj < nj; jj += 8 * kMvWaves) {
-      const int jb = jj + 4 * kMvWaves;
-      const bool hb = jb < nj;
-      const int qa = 3 * jj, qb = 3 * (hb ? jb : jj);
-      const double fa0 = sf[qa], fa1 = sf[qa + 1], fa2 = sf[qa + 2];
-      const double fb0 = sf[qb], fb1 = sf[qb + 1], fb2 = sf[qb + 2];
-      const double Ra0 = xi0 - sx[qa], Ra1 = xi1 - sx[qa + 1], Ra2 = xi2 - sx[qa + 2];
-      const double Rb0 = xi0 - sx[qb], Rb1 = xi1 - sx[qb + 1], Rb2 = xi2 - sx[qb + 2];
-      const double R2a = Ra0 * Ra0 + Ra1 * Ra1 + Ra2 * Ra2;
-      const double R2b = Rb0 * Rb0 + Rb1 * Rb1 + Rb2 * Rb2;
-      double cIa, cRRa, ya, cIb, cRRb, yb;
-      rpy_far_coeffs(R2a, kc, cIa, cRRa, ya);
-      rpy_far_coeffs(R2b, kc, cIb, cRRb, yb);
-      const bool na = !(R2a >= kc.a2x2), nb = !(R2b >= kc.a2x2);
-      if (na || nb) {  // rare: pairs closer than 2a
-        if (na) rpy_near_coeffs(R2a, ya, kc, cIa, cRRa);
-        if (nb) rpy_near_coeffs(R2b, yb, kc, cIb, cRRb);
+    for (int jt = 4 * w + jp; jt < nj; jt += 8 * kMvWaves) {
+#pragma unroll
+      for (int v = 0; v < kV; ++v) {
+        const int jj = jt + 4 * kW * v;  // phase 4 (w + kW v) + jp
+        if (jj >= nj) break;
+        const int jb = jj + 4 * kMvWaves;
+        const bool hb = jb < nj;
+        const int qa = 3 * jj, qb = 3 * (hb ? jb : jj);
+        const double fa0 = sf[qa], fa1 = sf[qa + 1], fa2 = sf[qa + 2];
+        const double fb0 = sf[qb], fb1 = sf[qb + 1], fb2 = sf[qb + 2];
+        const double Ra0 = xi0 - sx[qa], Ra1 = xi1 - sx[qa + 1], Ra2 = xi2 - sx[qa + 2];
+        const double Rb0 = xi0 - sx[qb], Rb1 = xi1 - sx[qb + 1], Rb2 = xi2 - sx[qb + 2];
+        const double R2a = Ra0 * Ra0 + Ra1 * Ra1 + Ra2 * Ra2;
+        const double R2b = Rb0 * Rb0 + Rb1 * Rb1 + Rb2 * Rb2;
+        double cIa, cRRa, ya, cIb, cRRb, yb;
+        rpy_far_coeffs(R2a, kc, cIa, cRRa, ya);
+        rpy_far_coeffs(R2b, kc, cIb, cRRb, yb);
+        const bool na = !(R2a >= kc.a2x2), nb = !(R2b >= kc.a2x2);
+        if (na || nb) {  // rare: pairs closer than 2a
+          if (na) rpy_near_coeffs(R2a, ya, kc, cIa, cRRa);
+          if (nb) rpy_near_coeffs(R2b, yb, kc, cIb, cRRb);
+        }
+        if (j0 + jj == ii) {  // D_ii = I
+          cIa = 1.0;
+          cRRa = 0.0;
+        }
+        if (j0 + jb == ii) {
+          cIb = 1.0;
+          cRRb = 0.0;
+        }
+        if (!hb) {  // past the chunk: no second bead
+          cIb = 0.0;
+          cRRb = 0.0;
+        }
+        const double rva = cRRa * (Ra0 * fa0 + Ra1 * fa1 + Ra2 * fa2);
+        const double rvb = cRRb * (Rb0 * fb0 + Rb1 * fb1 + Rb2 * fb2);
+        a0[v] += cIa * fa0 + rva * Ra0;
+        a1[v] += cIa * fa1 + rva * Ra1;
+        a2[v] += cIa * fa2 + rva * Ra2;
+        a0[v] += cIb * fb0 + rvb * Rb0;
+        a1[v] += cIb * fb1 + rvb * Rb1;
+        a2[v] += cIb * fb2 + rvb * Rb2;
       }
-      if (j0 + jj == ii) {  // D_ii = I
-        cIa = 1.0;
-        cRRa = 0.0;
-      }
-      if (j0 + jb == ii) {
-        cIb = 1.0;
-        cRRb = 0.0;
-      }
-      if (!hb) {  // past the chunk: no second bead
-        cIb = 0.0;
-        cRRb = 0.0;
-      }
-      const double rva = cRRa * (Ra0 * fa0 + Ra1 * fa1 + Ra2 * fa2);
-      const double rvb = cRRb * (Rb0 * fb0 + Rb1 * fb1 + Rb2 * fb2);
-      a0 += cIa * fa0 + rva * Ra0;
-      a1 += cIa * fa1 + rva * Ra1;
-      a2 += cIa * fa2 + rva * Ra2;
-      a0 += cIb * fb0 + rvb * Rb0;
-      a1 += cIb * fb1 + rvb * Rb1;
-      a2 += cIb * fb2 + rvb * Rb2;
     }
   }
-  // phases jp = 0..3 of this wave: lanes il, il+16, il+32, il+48
-  a0 += __shfl_xor(a0, 16, 64);
-  a1 += __shfl_xor(a1, 16, 64);
-  a2 += __shfl_xor(a2, 16, 64);
-  a0 += __shfl_xor(a0, 32, 64);
-  a1 += __shfl_xor(a1, 32, 64);
-  a2 += __shfl_xor(a2, 32, 64);
-  if (jp == 0) {
-    red[w][0][il] = a0;
-    red[w][1][il] = a1;
-    red[w][2][il] = a2;
+  // phases jp = 0..3 of a phase set: lanes il, il+16, il+32, il+48
+#pragma unroll
+  for (int v = 0; v < kV; ++v) {
+    double b0 = a0[v], b1 = a1[v], b2 = a2[v];
+    b0 += __shfl_xor(b0, 16, 64);
+    b1 += __shfl_xor(b1, 16, 64);
+    b2 += __shfl_xor(b2, 16, 64);
+    b0 += __shfl_xor(b0, 32, 64);
+    b1 += __shfl_xor(b1, 32, 64);
+    b2 += __shfl_xor(b2, 32, 64);
+    if (jp == 0) {
+      red[w + kW * v][0][il] = b0;
+      red[w + kW * v][1][il] = b1;
+      red[w + kW * v][2][il] = b2;
+    }
   }
   __syncthreads();
   if (tid < 3 * kMvI) {
@@ -343,11 +373,12 @@ __device__ __forceinline__ void dmatvec_body(int bx, const double* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(kMvThreads) void dmatvec_kernel(const double* __restrict__ x,
+__global__ __launch_bounds__(kMvThreads / 2) void dmatvec_kernel(const double* __restrict__ x,
                                                        const double* __restrict__ f,
                                                        double* __restrict__ r, int N, RpyConst kc,
                                                        const DevState* __restrict__ st) {
-  dmatvec_body<2048>(blockIdx.x, x, f, r, N, kc, st);
+  __shared__ double sx[3 * 2048], sf[3 * 2048], red[kMvLds];
+  dmatvec_body<2048, kMvThreads / 2>(blockIdx.x, x, f, r, N, kc, st, sx, sf, red);
 }
 
 // ------------------------------------------------------------ controller
@@ -499,17 +530,29 @@ __device__ void rod_forces(const double* z, const double* __restrict__ u,
 // is J with the roles of the rod directions u (forces) and the new rod
 // vectors Q (contraction) exchanged, the band arrays hold tri(J^T), and the
 // first product is D xbar.  xs then receives z = xbar - 2 Delta^T (Q mu).
+// The controller's LDS: the tridiagonal system, reduction slots and the
+// small GMRES state, carved from one arena of kCtlLds doubles.
+constexpr int kCtlLds = 4 * kPadRods + kCtlThreads / 64 + 8 * (kCtlThreads / 64) +
+                        2 * (kKmax + 1) + 2 * kKmax + (kKmax + 1) + kKmax + 2;
+
 template <bool kAdj>
 __device__ __forceinline__ void newton_controller_body(
     Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, double dt,
-    double bl, double tol, int maxit, DevState* __restrict__ st,
+    double bl, double tol, int maxit, DevState* __restrict__ st, double* arena,
     const double* __restrict__ xbar = nullptr) {
-  __shared__ double pa[kPadRods], pb[kPadRods], pc[kPadRods], pd[kPadRods];
-  __shared__ double red[kCtlThreads / 64];
-  __shared__ double red8[kCtlThreads / 64][8];
-  __shared__ double hcur[kKmax + 1], hsum[kKmax + 1];
-  __shared__ double cs_s[kKmax], sn_s[kKmax], s_s[kKmax + 1], y_s[kKmax];
-  __shared__ int sh_flag;
+  double* pa = arena;
+  double* pb = pa + kPadRods;
+  double* pc = pb + kPadRods;
+  double* pd = pc + kPadRods;
+  double* red = pd + kPadRods;
+  double(*red8)[8] = reinterpret_cast<double(*)[8]>(red + kCtlThreads / 64);
+  double* hcur = red + kCtlThreads / 64 + 8 * (kCtlThreads / 64);
+  double* hsum = hcur + (kKmax + 1);
+  double* cs_s = hsum + (kKmax + 1);
+  double* sn_s = cs_s + kKmax;
+  double* s_s = sn_s + kKmax;
+  double* y_s = s_s + (kKmax + 1);
+  int& sh_flag = *reinterpret_cast<int*>(y_s + kKmax);
   const int tid = threadIdx.x;
   const int M = N - 1;
   const int64_t n3 = 3 * (int64_t)N;
@@ -893,7 +936,97 @@ __device__ __forceinline__ void newton_controller_body(
 __global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
     Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, double dt,
     double bl, double tol, int maxit, DevState* __restrict__ st) {
-  newton_controller_body<false>(b, xs, T_out, N, dt, bl, tol, maxit, st);
+  __shared__ double arena[kCtlLds];
+  newton_controller_body<false>(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
+}
+
+// ------------------------------------------------ one launch per solve
+// The whole Newton-GMRES iteration in one launch of G <= (compute units)
+// workgroups of kCtlThreads, one per compute unit, every one resident at
+// once: each product with D is shared out by bead blocks (bx = g, g + G,
+// ...), then workgroup 0 runs the controller pass, with a grid barrier after
+// each phase.  The results are those of the alternating launches (the same
+// bodies; the product with two phase sets per wave sums in the same order).
+// Every barrier wait is bounded: a workgroup that waits longer than
+// kSpinLimit polls (the GPU did not run every workgroup at once) raises the
+// abort flag, every workgroup returns, and the solve reports
+// BD_ERR_NO_CONVERGE (positions not committed).
+constexpr int kPsLds = (kCtlLds > 6 * 2048 + kMvLds) ? kCtlLds : 6 * 2048 + kMvLds;
+constexpr long kSpinLimit = 1L << 21;
+
+__device__ bool grid_sync(GridBar* gb, uint32_t nwg, int* flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();  // this workgroup's writes, before its arrival
+    const uint32_t g = __hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived =
+        __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    if (arrived == nwg - 1) {
+      __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&gb->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long spins = 0;
+      while (__hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(&gb->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
+        }
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(&gb->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __threadfence();  // the other workgroups' writes, after the barrier
+    *flag = ok;
+  }
+  __syncthreads();
+  return *flag != 0;
+}
+
+// The two phases as separate functions, so that each gets its own register
+// allocation (inlined together they spill).
+__device__ __noinline__ void ps_matvec(int wg, int nwg, const double* __restrict__ x_old, Bufs b,
+                                       int N, RpyConst kc, double* arena) {
+  const int nblk = (N + kMvI - 1) / kMvI;
+  for (int blk = wg; blk < nblk; blk += nwg)
+    dmatvec_body<2048, kCtlThreads>(blk, x_old, b.f, b.r, N, kc, nullptr, arena,
+                                    arena + 3 * 2048, arena + 6 * 2048);
+}
+
+__device__ __noinline__ void ps_controller(Bufs b, double* __restrict__ xs,
+                                           double* __restrict__ T_out, int N, double dt, double bl,
+                                           double tol, int maxit, DevState* __restrict__ st,
+                                           double* arena) {
+  newton_controller_body<false>(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
+}
+
+__global__ __launch_bounds__(kCtlThreads) void constrain_persistent_kernel(
+    const double* __restrict__ x_old, Bufs b, double* __restrict__ xs,
+    double* __restrict__ T_out, int N, double dt, double bl, double tol, int maxit, RpyConst kc,
+    DevState* __restrict__ st, int cap) {
+  __shared__ double arena[kPsLds];
+  __shared__ int flag;
+  const uint32_t nwg = gridDim.x;
+  const int wg = blockIdx.x;
+  bool ok = true;
+  if (wg == 0) ps_controller(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
+  ok = grid_sync(b.gb, nwg, &flag);
+  for (int it = 0; ok && it < cap; ++it) {
+    if (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    ps_matvec(wg, (int)nwg, x_old, b, N, kc, arena);
+    if (!(ok = grid_sync(b.gb, nwg, &flag))) break;
+    if (wg == 0) ps_controller(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
+    ok = grid_sync(b.gb, nwg, &flag);
+  }
+  if (wg == 0 && threadIdx.x == 0 && (!ok || !st->done)) {
+    // a barrier was abandoned, or the launch cap ended the iteration first
+    if (st->status == BD_OK) st->status = BD_ERR_NO_CONVERGE;
+    st->done = 1;
+  }
 }
 
 // Adjoint of the tension solve: rod directions u at x_old, the new rod
@@ -949,7 +1082,8 @@ __global__ __launch_bounds__(256) void constrain_adjoint_init_kernel(
 __global__ __launch_bounds__(kCtlThreads) void adjoint_controller_kernel(
     Bufs b, const double* __restrict__ xbar, double* __restrict__ z, int N, double dt, double tol,
     DevState* __restrict__ st) {
-  newton_controller_body<true>(b, z, nullptr, N, dt, 1.0, tol, 0, st, xbar);
+  __shared__ double arena[kCtlLds];
+  newton_controller_body<true>(b, z, nullptr, N, dt, 1.0, tol, 0, st, arena, xbar);
 }
 
 // Ensembles: chain blockIdx.z of the table, its workspace carved in place;
@@ -961,20 +1095,23 @@ __global__ __launch_bounds__(256) void constrain_init_batched_kernel(
 }
 
 // One flattened grid over every chain's bead blocks (no idle workgroups).
-__global__ __launch_bounds__(kMvThreads) void dmatvec_batched_kernel(
+__global__ __launch_bounds__(kMvThreads / 2) void dmatvec_batched_kernel(
     const ChainDesc* __restrict__ cd, const int32_t* __restrict__ prefix, int count) {
   const int t = blockIdx.x;
   const int ci = find_chain(prefix, count, t);
   const ChainDesc& c = cd[ci];
   const Bufs b = carve(c.cons, c.N);
-  dmatvec_body<1024>(t - prefix[ci], c.x, b.f, b.r, c.N, rpy_const(c.hstar, c.a), c.st);
+  __shared__ double sx[3 * 1024], sf[3 * 1024], red[kMvLds];
+  dmatvec_body<1024, kMvThreads / 2>(t - prefix[ci], c.x, b.f, b.r, c.N, rpy_const(c.hstar, c.a),
+                                     c.st, sx, sf, red);
 }
 
 __global__ __launch_bounds__(kCtlThreads) void newton_controller_batched_kernel(
     const ChainDesc* __restrict__ cd) {
   const ChainDesc& c = cd[blockIdx.z];
+  __shared__ double arena[kCtlLds];
   newton_controller_body<false>(carve(c.cons, c.N), c.xs, nullptr, c.N, c.dt, c.b, c.tol, c.maxit,
-                                c.st);
+                                c.st, arena);
 }
 
 // States of `count` chains whose iteration the host stopped launching:
@@ -996,7 +1133,7 @@ int constrain_max_beads() { return kMaxRods + 1; }
 
 hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x_old, double* xs,
                             double* T_out, void* ws, DevState* st, DevState* host_state,
-                            int* pairs_hint) {
+                            int* pairs_hint, int n_cu) {
   const int N = p.n_beads;
   const int M = N - 1;
   Bufs b = carve(ws, N);
@@ -1005,6 +1142,16 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
   if (iblk < 16) iblk = 16;
   BD_LAUNCH("constrain_init", constrain_init_kernel, dim3(iblk), dim3(256), 0, s, x_old, xs, b, N,
             p.hstar, p.a, st);
+  if (n_cu > 0) {
+    // one launch: no host round trip, asynchronous on the stream
+    const int nblk = (N + kMvI - 1) / kMvI;
+    const int G = (nblk < n_cu) ? nblk : n_cu;
+    const int cap = (p.newton_maxit + 1) * (kKmax + 2);
+    BD_LAUNCH("constrain_persistent", constrain_persistent_kernel, dim3(G), dim3(kCtlThreads), 0,
+              s, x_old, b, xs, T_out, N, p.dt, p.b, p.newton_tol, p.newton_maxit,
+              rpy_const(p.hstar, p.a), st, cap);
+    return hipGetLastError();
+  }
   BD_LAUNCH("newton_controller", newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b, xs,
             T_out, N, p.dt, p.b, p.newton_tol, p.newton_maxit, st);
   const dim3 mvgrid((N + kMvI - 1) / kMvI);
@@ -1019,7 +1166,7 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
   while (launched < cap) {
     if (batch > cap - launched) batch = cap - launched;
     for (int c = 0; c < batch; ++c) {
-      BD_LAUNCH("dmatvec", dmatvec_kernel, mvgrid, dim3(kMvThreads), 0, s, x_old, b.f, b.r, N, kc,
+      BD_LAUNCH("dmatvec", dmatvec_kernel, mvgrid, dim3(kMvThreads / 2), 0, s, x_old, b.f, b.r, N, kc,
                 st);
       BD_LAUNCH("newton_controller", newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b,
                 xs, T_out, N, p.dt, p.b, p.newton_tol, p.newton_maxit, st);
@@ -1060,7 +1207,7 @@ hipError_t launch_constrain_adjoint(hipStream_t s, const bd_params_t& p, const d
   while (launched < cap) {
     if (batch > cap - launched) batch = cap - launched;
     for (int c = 0; c < batch; ++c) {
-      BD_LAUNCH("dmatvec", dmatvec_kernel, mvgrid, dim3(kMvThreads), 0, s, x_old, b.f, b.r, N, kc,
+      BD_LAUNCH("dmatvec", dmatvec_kernel, mvgrid, dim3(kMvThreads / 2), 0, s, x_old, b.f, b.r, N, kc,
                 st);
       BD_LAUNCH("adjoint_controller", adjoint_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s,
                 b, xbar, z, N, p.dt, p.newton_tol, st);
@@ -1083,7 +1230,7 @@ int constrain_mv_blocks(int n_beads) { return (n_beads + kMvI - 1) / kMvI; }
 hipError_t launch_dmatvec(hipStream_t s, const bd_params_t& p, const double* x, const double* f,
                           double* r, const DevState* st) {
   const int N = p.n_beads;
-  BD_LAUNCH("dmatvec", dmatvec_kernel, dim3((N + kMvI - 1) / kMvI), dim3(kMvThreads), 0, s, x, f,
+  BD_LAUNCH("dmatvec", dmatvec_kernel, dim3((N + kMvI - 1) / kMvI), dim3(kMvThreads / 2), 0, s, x, f,
             r, N, rpy_const(p.hstar, p.a), st);
   return hipGetLastError();
 }
@@ -1109,7 +1256,7 @@ hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int coun
   while (launched < cap) {
     if (batch > cap - launched) batch = cap - launched;
     for (int q = 0; q < batch; ++q) {
-      BD_LAUNCH("dmatvec_batched", dmatvec_batched_kernel, mvgrid, dim3(kMvThreads), 0, s, cd,
+      BD_LAUNCH("dmatvec_batched", dmatvec_batched_kernel, mvgrid, dim3(kMvThreads / 2), 0, s, cd,
                 mv_prefix, count);
       BD_LAUNCH("newton_controller_batched", newton_controller_batched_kernel, dim3(1, 1, count),
                 dim3(kCtlThreads), 0, s, cd);

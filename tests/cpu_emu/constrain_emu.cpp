@@ -5,7 +5,9 @@
 // buffer at exactly the documented size.  Values are meaningless there (no
 // barriers or cross-lane exchange), so the Newton-GMRES iteration runs to
 // its caps and every index range of the workspace is exercised.
-// Usage: constrain_emu n_beads newton_maxit skip_matvec(0|1)
+// Usage: constrain_emu n_beads newton_maxit skip_matvec(0|1) [one_launch(0|1)]
+// one_launch = 1 runs the one-launch solve with a single workgroup (its grid
+// barriers then never wait, so the sequential stand-in can run it).
 #include "../../paper_2208_06559_amd/csrc/constrain.hip"
 long g_emu_launches = 0;
 namespace bd {
@@ -14,7 +16,8 @@ void prof_mark_begin(hipStream_t, const char*) {}
 void prof_mark_end(hipStream_t) {}
 }  // namespace bd
 int main(int argc, char** argv) {
-  if (argc != 4) return 2;
+  if (argc != 4 && argc != 5) return 2;
+  const int ncu = (argc == 5) ? atoi(argv[4]) : 0;
   const int N = atoi(argv[1]), maxit = atoi(argv[2]);
   if (atoi(argv[3])) g_emu_skip = (const void*)&bd::dmatvec_kernel;
   bd_params_t p;
@@ -40,7 +43,7 @@ int main(int argc, char** argv) {
   bd::DevState* st = (bd::DevState*)calloc(1, sizeof(bd::DevState));
   bd::DevState* host = (bd::DevState*)calloc(1, sizeof(bd::DevState));
   int hint = 0;
-  const hipError_t e = bd::launch_constrain(nullptr, p, x, xs, T, ws, st, host, &hint);
+  const hipError_t e = bd::launch_constrain(nullptr, p, x, xs, T, ws, st, host, &hint, ncu);
   printf("N=%d maxit=%d: status %d, %ld launches, done %d\n", N, maxit, e, g_emu_launches,
          host->done);
   // the adjoint solve on the same workspace: exact-size xbar and z

@@ -65,6 +65,17 @@ inline int atomicMin(int* p, int v) { const int o = *p; if (v < o) *p = v; retur
 #define __builtin_amdgcn_sched_barrier(m) ((void)0)
 #define __builtin_amdgcn_s_barrier() ((void)0)
 #define __builtin_amdgcn_s_setprio(p) ((void)0)
+#define __builtin_amdgcn_s_sleep(n) ((void)0)
+#define __builtin_amdgcn_s_waitcnt(n) ((void)0)
+#define __noinline__ __attribute__((noinline))
+#define __HIP_MEMORY_SCOPE_AGENT 3
+// launches run one thread at a time: plain accesses stand in for atomics
+template <typename T> inline T emu_atomic_load(T* p) { return *p; }
+template <typename T, typename V> inline void emu_atomic_store(T* p, V v) { *p = (T)v; }
+template <typename T, typename V> inline T emu_atomic_fetch_add(T* p, V v) { const T o = *p; *p = o + (T)v; return o; }
+#define __hip_atomic_load(p, o, s) emu_atomic_load(p)
+#define __hip_atomic_store(p, v, o, s) emu_atomic_store((p), (v))
+#define __hip_atomic_fetch_add(p, v, o, s) emu_atomic_fetch_add((p), (v))
 template <typename T> inline T __shfl_xor(T v, int, int = 64) { return v; }
 extern long g_emu_launches;
 // Optional observer of every launch: kernel address, grid, and the

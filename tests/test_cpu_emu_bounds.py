@@ -79,6 +79,16 @@ def test_constrain_accesses_in_bounds(cemu, N, maxit, skip):
     assert "status 0" in r.stdout
 
 
+# The one-launch solve (grid barriers, the product with two phase sets per
+# wave, the controller passes) with one workgroup, whose barriers never wait.
+@pytest.mark.parametrize("N,maxit", [(2, 1), (3, 2), (37, 2), (300, 1)])
+def test_one_launch_constrain_accesses_in_bounds(cemu, N, maxit):
+    r = subprocess.run([cemu, str(N), str(maxit), "0", "1"], capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, (N, maxit, r.stderr[-3000:])
+    assert "status 0" in r.stdout
+
+
 # Ensembles: chains of uneven sizes (one panel or less, ragged last panels,
 # exact multiples of the step) factored in shared launches, each chain in
 # its own exact-size buffers; and the batched tension solve.
