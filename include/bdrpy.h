@@ -198,7 +198,7 @@ bd_status_t bd_brownian_noalloc(bd_handle_t h, const bd_params_t* p, int64_t ste
  * Inexact Newton from T = 0; each correction by GMRES right-preconditioned
  * with the tridiagonal part of the Jacobian; products with D are
  * matrix-free.  d_x_pred_inout: x* in, x^{t+dt} out (N x 3); d_T_out: N-1
- * or NULL.  N <= 4097 (BD_ERR_UNSUPPORTED above).  The call synchronises
+ * or NULL.  N <= 8193 (BD_ERR_UNSUPPORTED above).  The call synchronises
  * the stream a few times to stop the iteration once it has converged. */
 bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_old,
                          double* d_x_pred_inout, double* d_T_out, void* d_ws, size_t ws_bytes);
@@ -215,7 +215,7 @@ bd_status_t bd_constrain(bd_handle_t h, const bd_params_t* p, const double* d_x_
  * tridiagonal part of J^T (J with u and Q exchanged), products with D
  * matrix-free, to a residual of newton_tol |rhs| (BD_ERR_NO_CONVERGE in
  * bd_get_info otherwise).  d_ws: bd_workspace_size(BD_OP_CONSTRAIN, 3N)
- * bytes; N <= 4097.  Synchronises the stream a few times, as bd_constrain. */
+ * bytes; N <= 8193.  Synchronises the stream a few times, as bd_constrain. */
 bd_status_t bd_constrain_adjoint(bd_handle_t h, const bd_params_t* p, const double* d_x_old,
                                  const double* d_x_new, const double* d_xbar, double* d_z,
                                  void* d_ws, size_t ws_bytes);
@@ -232,15 +232,22 @@ bd_status_t bd_constrain_adjoint(bd_handle_t h, const bd_params_t* p, const doub
  * the factorisation (bd_cholesky_adjoint's Abar added into Dbar) and the
  * assembly (bd_rpy_assemble_adjoint of Dbar, Eqs. 7-9).  d_ws:
  * bd_workspace_size(BD_OP_STEP_ADJOINT, 3N, FP64) bytes (about four n x n
- * matrices plus bd_step's workspace); N <= 4097.  Status (pivot, tension or
+ * matrices plus bd_step's workspace); N <= 8193.  Status (pivot, tension or
  * adjoint non-convergence, coincident beads) via bd_get_info. */
 bd_status_t bd_step_adjoint(bd_handle_t h, const bd_params_t* p, int64_t step, const double* d_x,
                             double* d_xbar, double* d_hbar, double* d_kbar, void* d_ws,
                             size_t ws_bytes);
 
 /* One timestep of one chain: steps 1-5 above with noise counter `step`.
- * d_x_inout: N x 3, advanced in place, or left unchanged when the step
- * fails (non-positive pivot, tensions not converged; see bd_get_info). */
+ * d_x_inout: N x 3 (N <= 8193, BD_ERR_UNSUPPORTED above; the paper's
+ * longest chain, 6400 rods, is N = 6401), advanced in place, or left
+ * unchanged when the step fails (non-positive pivot, tensions not
+ * converged; see bd_get_info).  The tension solve synchronises the stream
+ * a few times, unless the handle was created with the environment variable
+ * BDRPY_CONSTRAIN=onelaunch: then the whole step is asynchronous on the
+ * stream (the solve runs as one launch with grid barriers, at most one
+ * workgroup per compute unit, which must all be resident at once) and can
+ * be captured in a HIP graph; a replay repeats the captured noise counter. */
 bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d_x_inout,
                     bd_precision_t prec, void* d_ws, size_t ws_bytes);
 
@@ -253,7 +260,7 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
  *   |Q_k'| = (|Y_k| + 2 dt K b) / (1 + 2 dt K) along Y_k (Eq. 17);
  * bead 0 moves by its explicit equation of motion,
  * x_0' = x_0 + dt (kappa.x_0 + v_0) + y_0, and x_{k+1}' = x_k' + Q_k'.
- * d_x_inout: N x 3 (N <= 4097, BD_ERR_UNSUPPORTED above), advanced in
+ * d_x_inout: N x 3 (N <= 8193, BD_ERR_UNSUPPORTED above), advanced in
  * place; d_ws: bd_workspace_size(BD_OP_STEP, 3N, prec) bytes.  max_rod_err
  * of bd_get_info receives max_k | |Q_k'|/b - 1 |; the Newton fields are 0.
  * A non-positive pivot leaves the positions unchanged. */

@@ -14,6 +14,7 @@
 
 namespace bd {
 int constrain_max_beads();
+int constrain_batched_max_beads();
 int fraenkel_max_beads();
 Profiler* profiler_new();
 void profiler_delete(Profiler* p);
@@ -636,7 +637,7 @@ static bool ensemble_args_ok(int32_t n_chains, const bd_params_t* p) {
 
 static bool ensemble_sizes_ok(int32_t n_chains, const bd_params_t* p) {
   for (int32_t c = 0; c < n_chains; ++c)
-    if (p[c].n_beads > bd::constrain_max_beads()) return false;
+    if (p[c].n_beads > bd::constrain_batched_max_beads()) return false;
   return true;
 }
 

@@ -30,6 +30,7 @@ namespace {
 constexpr int kKmax = 60;          // GMRES iterations per Newton step
 constexpr int kCtlThreads = 512;   // controller workgroup
 constexpr int kMaxRods = 4096;     // LDS capacity of the tridiagonal solve
+constexpr int kMaxRodsBig = 8192;  // longer chains: the tridiagonal system in global memory
 constexpr int kMvI = 16;           // beads i per matvec workgroup
 
 enum { PH_RESID = 0, PH_KRYLOV = 1, PH_ADJ_RHS = 2 };
@@ -53,6 +54,7 @@ struct Bufs {
   double *u, *Qs, *Q, *Gd, *Gp, *Gm, *T, *lo, *di, *up, *f, *r, *V, *H, *cs, *sn, *s;
   NewtonCtl* ctl;
   GridBar* gb;
+  double* tri;  // chains of more than kMaxRods rods: the tridiagonal system (4 x padded M)
 };
 
 
@@ -84,12 +86,15 @@ __host__ __device__ Bufs carve(void* ws, int N) {
   b.s = take(kKmax + 1);
   b.ctl = reinterpret_cast<NewtonCtl*>(take(8));
   b.gb = reinterpret_cast<GridBar*>(take(2));
+  b.tri = nullptr;
+  if (M > kMaxRods) b.tri = take(4 * (size_t)(M + M / 32 + 1));
   return b;
 }
 
 size_t carve_bytes(int N) {
   Bufs b = carve(nullptr, N);
-  return reinterpret_cast<size_t>(b.gb) + 256;
+  return (b.tri ? reinterpret_cast<size_t>(b.tri) + sizeof(double) * 4 * (size_t)((N - 1) + (N - 1) / 32 + 1)
+                : reinterpret_cast<size_t>(b.gb) + 256);
 }
 
 // RPY coefficients (Eqs. 8-9) for the matrix-free products, without
@@ -456,6 +461,7 @@ __device__ __forceinline__ double rcp_refined(double x) {
 // Every LDS read is unconditional (clamped index, contribution selected)
 // so that a level costs one LDS round trip.
 constexpr int kR = kMaxRods / kCtlThreads;  // unknowns per thread (k = tid + kCtlThreads q)
+constexpr int kRBig = kMaxRodsBig / kCtlThreads;
 
 __device__ __forceinline__ int lp(int i) { return i + (i >> 5); }  // padded LDS index
 constexpr int kPadRods = kMaxRods + kMaxRods / 32;
@@ -498,11 +504,12 @@ __device__ void cr_solve(int M, double* pa, double* pb, double* pc, double* pd) 
 // f_i = z_i u_i - z_{i-1} u_{i-1} with z in LDS (z_{-1} = z_{N-1} = 0).  The
 // bead loop has a fixed trip count and every load a valid (clamped) index, so
 // all loads of u issue together.
+template <int kRr = kR>
 __device__ void rod_forces(const double* z, const double* __restrict__ u,
                            double* __restrict__ f, int N) {
   const int M = N - 1;
 #pragma unroll
-  for (int q = 0; q <= kR; ++q) {
+  for (int q = 0; q <= kRr; ++q) {
     if (q % 3 == 0) __builtin_amdgcn_sched_barrier(0);  // loads in groups of three beads
     const int i = threadIdx.x + q * kCtlThreads;
     const int ic = (i < M) ? i : M - 1, im = (i > 0 && i - 1 < M) ? i - 1 : 0;
@@ -535,16 +542,22 @@ __device__ void rod_forces(const double* z, const double* __restrict__ u,
 constexpr int kCtlLds = 4 * kPadRods + kCtlThreads / 64 + 8 * (kCtlThreads / 64) +
                         2 * (kKmax + 1) + 2 * kKmax + (kKmax + 1) + kKmax + 2;
 
-template <bool kAdj>
+//
+// kRr = kRBig: chains of more than kMaxRods rods, the tridiagonal system in
+// global memory (b.tri; the same cyclic reduction, levels separated by the
+// workgroup barrier) and kRBig unknowns per thread.
+template <bool kAdj, int kRr = kR>
 __device__ __forceinline__ void newton_controller_body(
     Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, double dt,
     double bl, double tol, int maxit, DevState* __restrict__ st, double* arena,
     const double* __restrict__ xbar = nullptr) {
-  double* pa = arena;
-  double* pb = pa + kPadRods;
-  double* pc = pb + kPadRods;
-  double* pd = pc + kPadRods;
-  double* red = pd + kPadRods;
+  constexpr int kR = kRr;
+  const int ptri = (kRr == kRBig) ? (N - 1) + (N - 1) / 32 + 1 : kPadRods;
+  double* pa = (kRr == kRBig) ? b.tri : arena;
+  double* pb = pa + ptri;
+  double* pc = pb + ptri;
+  double* pd = pc + ptri;
+  double* red = arena + 4 * kPadRods;
   double(*red8)[8] = reinterpret_cast<double(*)[8]>(red + kCtlThreads / 64);
   double* hcur = red + kCtlThreads / 64 + 8 * (kCtlThreads / 64);
   double* hsum = hcur + (kKmax + 1);
@@ -610,7 +623,7 @@ __device__ __forceinline__ void newton_controller_body(
       ctl->eta = tol;
     }
     cr_solve(M, pa, pb, pc, pd);
-    rod_forces(pd, b.Q, b.f, N);
+    rod_forces<kRr>(pd, b.Q, b.f, N);
     return;
   }
   if (!kAdj && phase == PH_RESID) {
@@ -692,7 +705,7 @@ __device__ __forceinline__ void newton_controller_body(
       ctl->eta = eta_n;
     }
     cr_solve(M, pa, pb, pc, pd);
-    rod_forces(pd, b.u, b.f, N);
+    rod_forces<kRr>(pd, b.u, b.f, N);
     return;
   }
 
@@ -916,7 +929,7 @@ __device__ __forceinline__ void newton_controller_body(
       }
     }
     __syncthreads();
-    rod_forces(pa, b.u, b.f, N);
+    rod_forces<kRr>(pa, b.u, b.f, N);
     if (tid == 0) {
       ctl->newton_it = newton_it + 1;
       ctl->phase = PH_RESID;
@@ -928,16 +941,17 @@ __device__ __forceinline__ void newton_controller_body(
       if (k < M) pd[lp(k)] = wv[q];
     }
     cr_solve(M, pa, pb, pc, pd);
-    rod_forces(pd, kAdj ? b.Q : b.u, b.f, N);
+    rod_forces<kRr>(pd, kAdj ? b.Q : b.u, b.f, N);
     if (tid == 0) ctl->j = j + 1;
   }
 }
 
+template <int kRr>
 __global__ __launch_bounds__(kCtlThreads) void newton_controller_kernel(
     Bufs b, double* __restrict__ xs, double* __restrict__ T_out, int N, double dt,
     double bl, double tol, int maxit, DevState* __restrict__ st) {
   __shared__ double arena[kCtlLds];
-  newton_controller_body<false>(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
+  newton_controller_body<false, kRr>(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
 }
 
 // ------------------------------------------------ one launch per solve
@@ -997,13 +1011,15 @@ __device__ __noinline__ void ps_matvec(int wg, int nwg, const double* __restrict
                                     arena + 3 * 2048, arena + 6 * 2048);
 }
 
+template <int kRr>
 __device__ __noinline__ void ps_controller(Bufs b, double* __restrict__ xs,
                                            double* __restrict__ T_out, int N, double dt, double bl,
                                            double tol, int maxit, DevState* __restrict__ st,
                                            double* arena) {
-  newton_controller_body<false>(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
+  newton_controller_body<false, kRr>(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
 }
 
+template <int kRr>
 __global__ __launch_bounds__(kCtlThreads) void constrain_persistent_kernel(
     const double* __restrict__ x_old, Bufs b, double* __restrict__ xs,
     double* __restrict__ T_out, int N, double dt, double bl, double tol, int maxit, RpyConst kc,
@@ -1013,13 +1029,13 @@ __global__ __launch_bounds__(kCtlThreads) void constrain_persistent_kernel(
   const uint32_t nwg = gridDim.x;
   const int wg = blockIdx.x;
   bool ok = true;
-  if (wg == 0) ps_controller(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
+  if (wg == 0) ps_controller<kRr>(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
   ok = grid_sync(b.gb, nwg, &flag);
   for (int it = 0; ok && it < cap; ++it) {
     if (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
     ps_matvec(wg, (int)nwg, x_old, b, N, kc, arena);
     if (!(ok = grid_sync(b.gb, nwg, &flag))) break;
-    if (wg == 0) ps_controller(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
+    if (wg == 0) ps_controller<kRr>(b, xs, T_out, N, dt, bl, tol, maxit, st, arena);
     ok = grid_sync(b.gb, nwg, &flag);
   }
   if (wg == 0 && threadIdx.x == 0 && (!ok || !st->done)) {
@@ -1079,11 +1095,12 @@ __global__ __launch_bounds__(256) void constrain_adjoint_init_kernel(
   }
 }
 
+template <int kRr>
 __global__ __launch_bounds__(kCtlThreads) void adjoint_controller_kernel(
     Bufs b, const double* __restrict__ xbar, double* __restrict__ z, int N, double dt, double tol,
     DevState* __restrict__ st) {
   __shared__ double arena[kCtlLds];
-  newton_controller_body<true>(b, z, nullptr, N, dt, 1.0, tol, 0, st, arena, xbar);
+  newton_controller_body<true, kRr>(b, z, nullptr, N, dt, 1.0, tol, 0, st, arena, xbar);
 }
 
 // Ensembles: chain blockIdx.z of the table, its workspace carved in place;
@@ -1129,7 +1146,9 @@ __global__ void constrain_unfinished_kernel(DevState* st, int count) {
 
 size_t constrain_workspace_bytes(int64_t n_beads) { return carve_bytes((int)n_beads); }
 
-int constrain_max_beads() { return kMaxRods + 1; }
+int constrain_max_beads() { return kMaxRodsBig + 1; }
+
+int constrain_batched_max_beads() { return kMaxRods + 1; }
 
 hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x_old, double* xs,
                             double* T_out, void* ws, DevState* st, DevState* host_state,
@@ -1142,18 +1161,20 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
   if (iblk < 16) iblk = 16;
   BD_LAUNCH("constrain_init", constrain_init_kernel, dim3(iblk), dim3(256), 0, s, x_old, xs, b, N,
             p.hstar, p.a, st);
+  const bool big = M > kMaxRods;
   if (n_cu > 0) {
     // one launch: no host round trip, asynchronous on the stream
     const int nblk = (N + kMvI - 1) / kMvI;
     const int G = (nblk < n_cu) ? nblk : n_cu;
     const int cap = (p.newton_maxit + 1) * (kKmax + 2);
-    BD_LAUNCH("constrain_persistent", constrain_persistent_kernel, dim3(G), dim3(kCtlThreads), 0,
-              s, x_old, b, xs, T_out, N, p.dt, p.b, p.newton_tol, p.newton_maxit,
-              rpy_const(p.hstar, p.a), st, cap);
+    auto* ps = big ? constrain_persistent_kernel<kRBig> : constrain_persistent_kernel<kR>;
+    BD_LAUNCH("constrain_persistent", ps, dim3(G), dim3(kCtlThreads), 0, s, x_old, b, xs, T_out,
+              N, p.dt, p.b, p.newton_tol, p.newton_maxit, rpy_const(p.hstar, p.a), st, cap);
     return hipGetLastError();
   }
-  BD_LAUNCH("newton_controller", newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b, xs,
-            T_out, N, p.dt, p.b, p.newton_tol, p.newton_maxit, st);
+  auto* ctl = big ? newton_controller_kernel<kRBig> : newton_controller_kernel<kR>;
+  BD_LAUNCH("newton_controller", ctl, dim3(1), dim3(kCtlThreads), 0, s, b, xs, T_out, N, p.dt,
+            p.b, p.newton_tol, p.newton_maxit, st);
   const dim3 mvgrid((N + kMvI - 1) / kMvI);
   const RpyConst kc = rpy_const(p.hstar, p.a);
   // Each (matvec, controller) pair advances the iteration by one product with
@@ -1168,8 +1189,8 @@ hipError_t launch_constrain(hipStream_t s, const bd_params_t& p, const double* x
     for (int c = 0; c < batch; ++c) {
       BD_LAUNCH("dmatvec", dmatvec_kernel, mvgrid, dim3(kMvThreads / 2), 0, s, x_old, b.f, b.r, N, kc,
                 st);
-      BD_LAUNCH("newton_controller", newton_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s, b,
-                xs, T_out, N, p.dt, p.b, p.newton_tol, p.newton_maxit, st);
+      BD_LAUNCH("newton_controller", ctl, dim3(1), dim3(kCtlThreads), 0, s, b, xs, T_out, N,
+                p.dt, p.b, p.newton_tol, p.newton_maxit, st);
     }
     launched += batch;
     hipError_t e = hipMemcpyAsync(host_state, st, sizeof(DevState), hipMemcpyDeviceToHost, s);
@@ -1200,6 +1221,7 @@ hipError_t launch_constrain_adjoint(hipStream_t s, const bd_params_t& p, const d
             x_old, x_new, xbar, b, N, p.hstar, p.a, p.dt, st);
   const dim3 mvgrid((N + kMvI - 1) / kMvI);
   const RpyConst kc = rpy_const(p.hstar, p.a);
+  auto* actl = (M > kMaxRods) ? adjoint_controller_kernel<kRBig> : adjoint_controller_kernel<kR>;
   // (matvec, controller) pairs: the first gives D xbar and the right side,
   // each further one a Krylov step; the host polls as for the forward solve
   const int cap = kKmax + 2;
@@ -1209,8 +1231,8 @@ hipError_t launch_constrain_adjoint(hipStream_t s, const bd_params_t& p, const d
     for (int c = 0; c < batch; ++c) {
       BD_LAUNCH("dmatvec", dmatvec_kernel, mvgrid, dim3(kMvThreads / 2), 0, s, x_old, b.f, b.r, N, kc,
                 st);
-      BD_LAUNCH("adjoint_controller", adjoint_controller_kernel, dim3(1), dim3(kCtlThreads), 0, s,
-                b, xbar, z, N, p.dt, p.newton_tol, st);
+      BD_LAUNCH("adjoint_controller", actl, dim3(1), dim3(kCtlThreads), 0, s, b, xbar, z, N, p.dt,
+                p.newton_tol, st);
     }
     launched += batch;
     hipError_t e = hipMemcpyAsync(host_state, st, sizeof(DevState), hipMemcpyDeviceToHost, s);

@@ -17,7 +17,7 @@ namespace bd {
 namespace {
 
 constexpr int kFrThreads = 1024;  // one workgroup: links k = tid + 1024 q
-constexpr int kFrMaxLinks = 4096;
+constexpr int kFrMaxLinks = 8192;
 constexpr int kFrPer = kFrMaxLinks / kFrThreads;
 
 __device__ __forceinline__ void spring_force(const double* __restrict__ x, int k, double K,

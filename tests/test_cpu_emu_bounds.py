@@ -71,7 +71,8 @@ def test_cholesky_accesses_in_bounds(emu, n, ld_pad, prec):
 # (beads, Newton iteration cap, skip the matrix-free product threads): the
 # largest chain the solve supports runs with the O(N^2) product skipped.
 @pytest.mark.parametrize("N,maxit,skip", [(2, 1, 0), (3, 2, 0), (37, 2, 0), (300, 1, 0),
-                                          (1025, 1, 1), (4097, 2, 1)])
+                                          (1025, 1, 1), (4097, 2, 1), (4098, 1, 1),
+                                          (8193, 2, 1)])
 def test_constrain_accesses_in_bounds(cemu, N, maxit, skip):
     r = subprocess.run([cemu, str(N), str(maxit), str(skip)], capture_output=True, text=True,
                        timeout=300)

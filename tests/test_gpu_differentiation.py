@@ -81,7 +81,8 @@ def test_cholesky_adjoint_of_gpu_factor_half_norm(h):
     assert err <= 1e-12, err
 
 
-@pytest.mark.parametrize("N,hstar", [(2, 0.25), (7, 0.0), (40, 0.25), (300, 0.5), (1025, 0.25)])
+@pytest.mark.parametrize("N,hstar", [(2, 0.25), (7, 0.0), (40, 0.25), (300, 0.5), (1025, 0.25),
+                                     (4500, 0.25)])
 def test_constrain_adjoint_vs_oracle(h, N, hstar):
     pg = B.make_params(N, hstar=hstar, dt=1e-3)
     po = o.make_params(N, hstar=hstar, dt=1e-3)

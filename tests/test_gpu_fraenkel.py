@@ -82,6 +82,6 @@ def test_fraenkel_argument_errors(h):
     for K in (0.0, -1.0, float("inf")):
         assert L.bd_step_fraenkel(h._h, C.byref(pg), K, 0, x.data_ptr(), 0, ws.data_ptr(),
                                   ws.numel()) == B.ERR_PARAM
-    big = B.make_params(4098)
+    big = B.make_params(8194)
     assert L.bd_step_fraenkel(h._h, C.byref(big), 1e3, 0, x.data_ptr(), 0, ws.data_ptr(),
                               ws.numel()) == B.ERR_UNSUPPORTED

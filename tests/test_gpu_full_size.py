@@ -144,3 +144,31 @@ def test_step_full_size(h):
             rods = np.linalg.norm(np.diff(xn, axis=0), axis=1)
             assert np.abs(rods - W.b).max() <= 1e-10, (s, prec)
         x = xo
+
+
+@pytest.mark.parametrize("Nb", [6400, 4101])
+def test_step_longest_chain(h, Nb):
+    """Chains beyond 4097 beads (the tridiagonal system of the tension solve
+    in global memory): N = 6400 beads, n = 19200, the paper's longest chain
+    (6399 rods, Section 4's largest matrix order), and N = 4101, just past
+    the in-LDS solve; uniaxial extension at Wi = 5, one step of each
+    precision from the oracle's start."""
+    rate = 5.0 / I.relaxation_time(Nb)
+    kw = dict(dt=W.dt, kappa=I.kappa_for("uniaxial", rate), seed=W.seed, hstar=W.hstar, a=W.a,
+              b=W.b)
+    pg, po = B.make_params(Nb, **kw), o.make_params(Nb, **kw)
+    x = I.random_walk(Nb, W.b, W.seed)
+    xo, io = o.step(po, 0, x)
+    assert io["status"] == o.OK
+    for prec, tol in ((B.PREC_FP64, 1e-10), (B.PREC_MIXED, 1e-6)):
+        xg = torch.tensor(x, dtype=torch.float64, device=DEV)
+        h.step(pg, 0, xg, prec)
+        st = h.info()
+        assert st["status"] == B.OK, (prec, st)
+        xn = xg.cpu().numpy()
+        err = np.abs(xn - xo).max() / W.b
+        print(f"N = {Nb} prec {prec}: max |dr|/b vs oracle {err:.3e}, newton "
+              f"{st['newton_iters']}, krylov {st['krylov_iters']}", flush=True)
+        assert err <= tol, (prec, err)
+        rods = np.linalg.norm(np.diff(xn, axis=0), axis=1)
+        assert np.abs(rods - W.b).max() <= 1e-10, prec

@@ -35,7 +35,8 @@ def handles():
 
 
 @pytest.mark.parametrize("N,prec", [(2, B.PREC_FP64), (33, B.PREC_FP64), (300, B.PREC_MIXED),
-                                    (1025, B.PREC_FP64), (4096, B.PREC_MIXED)])
+                                    (1025, B.PREC_FP64), (4096, B.PREC_MIXED),
+                                    (5000, B.PREC_FP64)])
 def test_onelaunch_equals_polled_bitwise(handles, N, prec):
     h0, h1 = handles
     w = I.LONG_UNIAXIAL
