@@ -263,7 +263,7 @@ def ensemble_leg(B, I, torch, np, precs, args, dev) -> dict:
     flops = float(sum(chol_flops(3 * int(v)) for v in sizes))
     out = {"workload": w.name, "chains": int(w.chains), "n_beads_min": int(sizes.min()),
            "n_beads_max": int(sizes.max()), "sum_n3_over_3": flops}
-    h = B.Handle(0)
+    h = B.Handle(0, tuned=True)
     warm = 2
     for name, prec in precs.items():
         xp = x0.clone()
@@ -285,6 +285,19 @@ def ensemble_leg(B, I, torch, np, precs, args, dev) -> dict:
         h.profile_begin()
         ens.step(warm + args.ensemble_steps)
         prof = h.profile_end()
+        # the same steps replayed from a captured HIP graph
+        ens.capture()
+        s0 = warm + args.ensemble_steps + 1
+        ens.step(s0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.ensemble_steps):
+            ens.step(s0 + 1 + s)
+        torch.cuda.synchronize()
+        gwall = time.perf_counter() - t0
+        ginfos = ens.info()
+        if any(i["status"] != B.OK for i in ginfos):
+            raise RuntimeError(f"ensemble {name} captured steps failed")
         ms = 1e3 * wall / args.ensemble_steps
         chol = {k: v for k, v in prof.items()
                 if k.startswith(("potrf", "panel_solve", "syrk"))}
@@ -298,9 +311,12 @@ def ensemble_leg(B, I, torch, np, precs, args, dev) -> dict:
             "cholesky_kernels_ms_per_step": sum(v[1] for v in chol.values()),
             "max_newton_iters": max(i["newton_iters"] for i in infos),
             "max_rod_err": max(i["max_rod_err"] for i in infos),
+            "graph_ensemble_steps_per_s": args.ensemble_steps / gwall,
+            "graph_ms_per_step": 1e3 * gwall / args.ensemble_steps,
         }
         log(f"ensemble {name}: {out[name]['ensemble_steps_per_s']:.2f} steps/s "
-            f"({ms:.3f} ms/step, {out[name]['chain_steps_per_s']:.0f} chain-steps/s)")
+            f"({ms:.3f} ms/step, {out[name]['chain_steps_per_s']:.0f} chain-steps/s); "
+            f"captured graph {out[name]['graph_ms_per_step']:.3f} ms/step")
         ens.close()
         del ens, xp
         torch.cuda.empty_cache()
@@ -410,7 +426,7 @@ def main() -> int:
     p = B.make_params(N, **kw)
     x0_np = w.initial()
     x0 = torch.tensor(x0_np, dtype=torch.float64, device=dev)
-    h = B.Handle(0)
+    h = B.Handle(0, tuned=True)  # the autotuner's schedules, if tuning.json exists
     precs = {"mixed": B.PREC_MIXED, "fp64": B.PREC_FP64}
     if args.only != "all":
         precs = {args.only: precs[args.only]}
@@ -658,6 +674,8 @@ def main() -> int:
         "ensemble": ens,
         "fraenkel": fraenkel,
         "context": extra,
+        "tuning": ({"schedules": h.tuning["schedules"], "ensemble_panels": h.tuning["ensemble_panels"],
+                    "source": "paper_2208_06559_amd/tuning.json"} if h.tuning else None),
     }
     print(json.dumps(out), flush=True)
     h.close()

@@ -113,6 +113,30 @@ bd_status_t bd_create(bd_handle_t* h, int device, void* hip_stream);
 bd_status_t bd_destroy(bd_handle_t h);
 bd_status_t bd_set_stream(bd_handle_t h, void* hip_stream);
 
+/* Factorisation schedule for calls of matrix order n <= n_max in precision
+ * prec (the first matching row of the handle's table applies): the trailing
+ * matrix is updated by up to step_panels (1, 2 or 4) panels of 128 columns
+ * per pass while more than wide_rows rows remain, by two after.  Results of
+ * different schedules differ only in rounding order. */
+typedef struct {
+  int64_t n_max;
+  int32_t prec;         /* bd_precision_t */
+  int32_t step_panels;  /* 1, 2 or 4 */
+  int64_t wide_rows;    /* >= 0 */
+} bd_schedule_t;
+
+/* Copy a table of schedules into the handle (count = 0: back to the
+ * defaults, four panels while more than 4096 rows remain, or the
+ * BDRPY_STEP_PANELS / BDRPY_WIDE_ROWS environment variables read at
+ * bd_create).  The table is meant to come from measured timings: the
+ * package's autotuner (tune.py) writes one for this GPU. */
+bd_status_t bd_set_schedules(bd_handle_t h, const bd_schedule_t* rows, int32_t count);
+
+/* Panels per factorisation step (2 or 4; 0: the default, four, or
+ * BDRPY_ENS_PANELS) of the ensembles created on this handle afterwards, in
+ * precision prec. */
+bd_status_t bd_set_ensemble_panels(bd_handle_t h, bd_precision_t prec, int32_t panels);
+
 /* Bytes of device workspace the operation needs for matrix order n = 3N
  * (for BD_OP_CHOLESKY, n is the matrix order of the call). */
 bd_status_t bd_workspace_size(bd_op_t op, int64_t n, bd_precision_t prec, size_t* bytes);
@@ -339,6 +363,20 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
  * and those of the others are reported by bd_ensemble_get_info.  The call
  * synchronises the stream a few times during the tension solves. */
 bd_status_t bd_ensemble_step(bd_ensemble_t e, int64_t step);
+
+/* Capture one step of the ensemble in a HIP graph; from then on
+ * bd_ensemble_step replays it (one graph launch per step, no host round
+ * trip: asynchronous on the handle's stream).  The captured step differs
+ * from the plain one in two ways: its noise counter is kept on the device
+ * (set from `step` when a call does not follow the previous one, advanced
+ * by each replay), and its tension solves take exactly max_products
+ * (product with D, controller) pairs (0: 5/4 of the products the previous
+ * plain step needed plus 4), launches for a converged chain returning at
+ * once; a chain that needs more reports BD_ERR_NO_CONVERGE in
+ * bd_ensemble_get_info and keeps its positions.  Results are otherwise
+ * bitwise those of plain steps.  Not with profiling on (BD_ERR_PARAM);
+ * BD_ERR_HIP if the capture fails. */
+bd_status_t bd_ensemble_capture(bd_ensemble_t e, int32_t max_products);
 
 /* Synchronise and write the info of the last step of every chain to
  * out[0..n_chains-1], in the order of p. */

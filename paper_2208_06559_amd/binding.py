@@ -38,7 +38,8 @@ EXPORTS = ("bd_create", "bd_destroy", "bd_set_stream", "bd_workspace_size", "bd_
            "bd_ensemble_destroy", "bd_step_fraenkel", "bd_observables",
            "bd_rpy_assemble_adjoint", "bd_brownian_adjoint", "bd_brownian_noalloc",
            "bd_stress", "bd_cholesky_adjoint", "bd_constrain_adjoint",
-           "bd_step_adjoint")
+           "bd_step_adjoint", "bd_ensemble_capture", "bd_set_schedules",
+           "bd_set_ensemble_panels")
 
 
 class BdError(RuntimeError):
@@ -98,6 +99,25 @@ def make_params(n_beads: int, *, b=1.0, hstar=0.25, a=0.5, dt=1e-4, kappa=None, 
     return p
 
 
+class Schedule(C.Structure):
+    """Mirror of bd_schedule_t."""
+    _fields_ = [("n_max", C.c_int64), ("prec", C.c_int32), ("step_panels", C.c_int32),
+                ("wide_rows", C.c_int64)]
+
+
+TUNING_PATH = os.path.join(HERE, "tuning.json")
+
+
+def load_tuning(path: str = TUNING_PATH) -> dict | None:
+    """The autotuner's table (tune.py), or None when there is none."""
+    import json
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
 class KernelStat(C.Structure):
     """Mirror of bd_kernel_stat_t."""
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
@@ -132,6 +152,9 @@ def lib():
         L.bd_ensemble_step.argtypes = [vp, C.c_int64]
         L.bd_ensemble_get_info.argtypes = [vp, C.POINTER(Info)]
         L.bd_ensemble_destroy.argtypes = [vp]
+        L.bd_ensemble_capture.argtypes = [vp, C.c_int32]
+        L.bd_set_schedules.argtypes = [vp, C.POINTER(Schedule), C.c_int32]
+        L.bd_set_ensemble_panels.argtypes = [vp, C.c_int, C.c_int32]
         L.bd_step_fraenkel.argtypes = [vp, pp, C.c_double, C.c_int64, dp, C.c_int, vp, C.c_size_t]
         L.bd_observables.argtypes = [vp, C.c_int32, dp, vp, dp]
         L.bd_rpy_assemble_adjoint.argtypes = [vp, pp, dp, dp, C.c_int64, dp, dp, vp, C.c_size_t]
@@ -180,7 +203,8 @@ class Handle:
     """One bd_handle_t on the current device, launching on torch's current
     stream at the time of each call."""
 
-    def __init__(self, device: int | None = None):
+    def __init__(self, device: int | None = None, tuned: bool = False):
+        """tuned: apply the autotuner's committed table (tuning.json), if any."""
         dev = torch.cuda.current_device() if device is None else int(device)
         self.device = dev
         h = C.c_void_p()
@@ -190,6 +214,25 @@ class Handle:
         self._h = h
         self._ws = {}
         self._ensembles = weakref.WeakSet()  # destroyed before the handle
+        self.tuning = None
+        if tuned:
+            t = load_tuning()
+            if t is not None:
+                self.set_schedules(t["schedules"])
+                for name, prec in (("fp64", PREC_FP64), ("mixed", PREC_MIXED)):
+                    self.set_ensemble_panels(prec, int(t["ensemble_panels"][name]))
+                self.tuning = t
+
+    def set_schedules(self, rows):
+        """bd_set_schedules from dicts with n_max, prec, step_panels, wide_rows."""
+        arr = (Schedule * max(len(rows), 1))()
+        for i, r in enumerate(rows):
+            arr[i] = Schedule(int(r["n_max"]), int(r["prec"]), int(r["step_panels"]),
+                              int(r["wide_rows"]))
+        _check(lib().bd_set_schedules(self._h, arr, len(rows)), "bd_set_schedules")
+
+    def set_ensemble_panels(self, prec: int, panels: int):
+        _check(lib().bd_set_ensemble_panels(self._h, prec, panels), "bd_set_ensemble_panels")
 
     def close(self):
         if self._h:
@@ -423,6 +466,10 @@ class Ensemble:
     def step(self, step: int):
         self.handle._sync_stream()
         _check(lib().bd_ensemble_step(self._e, step), "bd_ensemble_step")
+
+    def capture(self, max_products: int = 0):
+        """bd_ensemble_capture: later steps replay one captured HIP graph."""
+        _check(lib().bd_ensemble_capture(self._e, int(max_products)), "bd_ensemble_capture")
 
     def info(self) -> list[dict]:
         out = (Info * self.count)()

@@ -36,7 +36,25 @@ struct bd_handle_s {
   bool tile_potrf;     // Cholesky diagonal blocks on matrix cores
   void* scratch;       // this device's fixed scratch array (bd_brownian_noalloc)
   int ps_cu;           // workgroups of the one-launch tension solve (0: host-polled launches)
+  std::vector<bd_schedule_t> sched;  // tuned factorisation schedules (bd_set_schedules)
+  int ens_panels[2];   // ensembles' panels per factorisation step, by precision (0: default)
 };
+
+namespace {
+// The factorisation schedule of a call of matrix order n: the first tuned
+// row that covers (n, prec), else the handle's defaults.
+void schedule_for(const bd_handle_s* h, int64_t n, bd_precision_t prec, int& panels,
+                  int64_t& wide) {
+  for (const bd_schedule_t& r : h->sched)
+    if (r.prec == (int32_t)prec && n <= r.n_max) {
+      panels = r.step_panels;
+      wide = r.wide_rows;
+      return;
+    }
+  panels = h->step_panels;
+  wide = h->wide_rows;
+}
+}  // namespace
 
 namespace {
 
@@ -153,6 +171,13 @@ __global__ void reset_states_kernel(DevState* st, int count) {
   }
 }
 
+// *d = v, or *d += 1 (advance): the device noise counter of a captured
+// ensemble step.
+__global__ void set_step_kernel(int64_t* d, int64_t v, int advance) {
+  if (advance) *d += 1;
+  else *d = v;
+}
+
 __global__ void commit_positions_batched_kernel(const bd::ChainDesc* cd) {
   const bd::ChainDesc& c = cd[blockIdx.z];
   if (c.st->status != BD_OK) return;
@@ -172,6 +197,14 @@ struct CallScope {
 bd_status_t enter(bd_handle_t h) {
   if (!h) return BD_ERR_PARAM;
   return hip_status(hipSetDevice(h->device));
+}
+
+hipError_t launch_cholesky_tuned(bd_handle_t h, hipStream_t s, int64_t n, double* A, int64_t ld,
+                                 bd_precision_t prec, void* ws) {
+  int sp;
+  int64_t wr;
+  schedule_for(h, n, prec, sp, wr);
+  return bd::launch_cholesky(s, h->aux, h->ev, n, A, ld, prec, ws, h->st, sp, wr, h->tile_potrf);
 }
 
 hipError_t reset(bd_handle_t h) {
@@ -199,6 +232,14 @@ struct bd_ensemble_s {
   int mv_blocks, rpy_blocks, trmv_blocks;
   bd::BatchTables tb;                // flattened grids of the factorisation
   int32_t* tb_dev;                   // device copy of tb.host
+  // a captured step (bd_ensemble_capture): its executable graph, the stream
+  // it was captured on, the device noise counter it reads and advances, and
+  // the counter the host expects there
+  hipGraphExec_t gexec;
+  hipStream_t cap;
+  int64_t* d_step;
+  int64_t next_step;
+  int budget;
 };
 
 extern "C" {
@@ -237,6 +278,7 @@ bd_status_t bd_create(bd_handle_t* out, int device, void* hip_stream) {
   h->aux = nullptr;
   h->ev[0] = h->ev[1] = h->ev[2] = h->ev[3] = nullptr;
   h->scratch = nullptr;
+  h->ens_panels[0] = h->ens_panels[1] = 0;
   // The tension solve alternates launches of the product with D and the
   // controller, polled by the host; BDRPY_CONSTRAIN=onelaunch runs it as one
   // launch of at most one workgroup per compute unit instead (no host round
@@ -298,6 +340,28 @@ bd_status_t bd_set_stream(bd_handle_t h, void* hip_stream) {
   return BD_OK;
 }
 
+bd_status_t bd_set_schedules(bd_handle_t h, const bd_schedule_t* rows, int32_t count) {
+  if (!h || count < 0 || (count > 0 && !rows)) return BD_ERR_PARAM;
+  for (int32_t i = 0; i < count; ++i) {
+    const bd_schedule_t& r = rows[i];
+    if (!prec_ok((bd_precision_t)r.prec) || r.n_max < 1 || r.wide_rows < 0 ||
+        (r.step_panels != 1 && r.step_panels != 2 && r.step_panels != 4))
+      return BD_ERR_PARAM;
+  }
+  try {
+    h->sched.assign(rows, rows + count);
+  } catch (...) {
+    return BD_ERR_ALLOC;
+  }
+  return BD_OK;
+}
+
+bd_status_t bd_set_ensemble_panels(bd_handle_t h, bd_precision_t prec, int32_t panels) {
+  if (!h || !prec_ok(prec) || (panels != 0 && panels != 2 && panels != 4)) return BD_ERR_PARAM;
+  h->ens_panels[prec == BD_PREC_MIXED ? 1 : 0] = panels;
+  return BD_OK;
+}
+
 bd_status_t bd_workspace_size(bd_op_t op, int64_t n, bd_precision_t prec, size_t* bytes) {
   if (!bytes || n < 1 || !prec_ok(prec)) return BD_ERR_PARAM;
   switch (op) {
@@ -347,8 +411,11 @@ bd_status_t bd_cholesky(bd_handle_t h, int64_t n, double* d_A, int64_t ld, bd_pr
   if (n < 1 || !d_A || ld < n || !prec_ok(prec) || !d_ws) return BD_ERR_PARAM;
   if (ws_bytes < bd::cholesky_workspace_bytes(n, prec)) return BD_ERR_PARAM;
   if (reset(h) != hipSuccess) return BD_ERR_HIP;
+  int sp;
+  int64_t wr;
+  schedule_for(h, n, prec, sp, wr);
   return hip_status(bd::launch_cholesky(h->stream, h->aux, h->ev, n, d_A, ld, prec, d_ws, h->st,
-                                              h->step_panels, h->wide_rows, h->tile_potrf));
+                                        sp, wr, h->tile_potrf));
 }
 
 bd_status_t bd_cholesky_adjoint(bd_handle_t h, int64_t n, const double* d_L, int64_t ld,
@@ -424,8 +491,7 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
   hipError_t he = reset(h);
   if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
   if (he == hipSuccess)
-    he = bd::launch_cholesky(s, h->aux, h->ev, n, D, ld, prec, base + L.chol, h->st,
-                              h->step_panels, h->wide_rows, h->tile_potrf);
+    he = launch_cholesky_tuned(h, s, n, D, ld, prec, base + L.chol);
   if (he == hipSuccess)
     he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);
@@ -482,8 +548,7 @@ bd_status_t bd_step_adjoint(bd_handle_t h, const bd_params_t* p, int64_t step, c
   hipError_t he = reset(h);
   if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
   if (he == hipSuccess)
-    he = bd::launch_cholesky(s, h->aux, h->ev, n, D, ld, BD_PREC_FP64, fwd + L.chol, h->st,
-                              h->step_panels, h->wide_rows, h->tile_potrf);
+    he = launch_cholesky_tuned(h, s, n, D, ld, BD_PREC_FP64, fwd + L.chol);
   if (he == hipSuccess) he = bd::launch_brownian(s, *p, step, D, ld, y, xi, fwd + L.brown);
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);
   if (he == hipSuccess)
@@ -533,8 +598,7 @@ bd_status_t bd_step_fraenkel(bd_handle_t h, const bd_params_t* p, double k_sprin
   hipError_t he = reset(h);
   if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
   if (he == hipSuccess)
-    he = bd::launch_cholesky(s, h->aux, h->ev, n, D, ld, prec, base + L.chol, h->st,
-                              h->step_panels, h->wide_rows, h->tile_potrf);
+    he = launch_cholesky_tuned(h, s, n, D, ld, prec, base + L.chol);
   if (he == hipSuccess)
     he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
   if (he == hipSuccess) he = bd::launch_spring_forces(s, d_x, p->n_beads, k_spring, p->b, f);
@@ -652,6 +716,9 @@ bd_status_t bd_ensemble_workspace_size(int32_t n_chains, const bd_params_t* p,
 }
 
 static void ensemble_release(bd_ensemble_s* e) {
+  if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+  if (e->cap) (void)hipStreamDestroy(e->cap);
+  if (e->d_step) (void)hipFree(e->d_step);
   if (e->cd) (void)hipFree(e->cd);
   if (e->mv_prefix) (void)hipFree(e->mv_prefix);
   if (e->rpy_prefix) (void)hipFree(e->rpy_prefix);
@@ -698,11 +765,18 @@ static bd_status_t ensemble_create_impl(bd_handle_t h, int32_t n_chains, const b
   e->mv_prefix = e->rpy_prefix = e->trmv_prefix = nullptr;
   e->mv_blocks = e->rpy_blocks = e->trmv_blocks = 0;
   e->tb_dev = nullptr;
+  e->gexec = nullptr;
+  e->cap = nullptr;
+  e->d_step = nullptr;
+  e->next_step = -1;
+  e->budget = 0;
   // BDRPY_ENS_PANELS=2 takes two-panel factorisation steps (for
   // comparisons); by default four: with many chains sharing each launch the
   // trailing updates, not the chain of diagonal blocks, bound the time.
   const char* ep = getenv("BDRPY_ENS_PANELS");
   e->step_panels = (ep && ep[0] == '2') ? 2 : 4;
+  if (h->ens_panels[prec == BD_PREC_MIXED ? 1 : 0] > 0)  // tuned (bd_set_ensemble_panels)
+    e->step_panels = h->ens_panels[prec == BD_PREC_MIXED ? 1 : 0];
   if (hipMalloc(&e->cd, sizeof(bd::ChainDesc) * (size_t)n_chains) != hipSuccess ||
       hipMalloc(&e->st, sizeof(DevState) * (size_t)n_chains) != hipSuccess ||
       hipHostMalloc(&e->host_st, sizeof(DevState) * (size_t)n_chains, hipHostMallocDefault) !=
@@ -819,13 +893,12 @@ bd_status_t bd_ensemble_create(bd_handle_t h, int32_t n_chains, const bd_params_
   }
 }
 
-bd_status_t bd_ensemble_step(bd_ensemble_t e, int64_t step) {
-  if (!e) return BD_ERR_PARAM;
+// The launches of one ensemble step on stream s: polled tension solves
+// (budget 0, noise counter `step`) or, for a captured step, a fixed number
+// of products, the noise counter read from d_step and advanced at the end.
+static hipError_t ensemble_step_launches(bd_ensemble_s* e, hipStream_t s, int64_t step,
+                                         const int64_t* d_step, int budget) {
   bd_handle_t h = e->h;
-  CallScope scope(h);
-  bd_status_t err = enter(h);
-  if (err != BD_OK) return err;
-  hipStream_t s = h->stream;
   const int z = e->count;
   const int64_t max_n = 3 * (int64_t)e->max_beads;
   BD_LAUNCH("reset_states", reset_states_kernel, dim3((unsigned)((z + 255) / 256)), dim3(256), 0,
@@ -837,17 +910,75 @@ bd_status_t bd_ensemble_step(bd_ensemble_t e, int64_t step) {
     he = bd::launch_cholesky_batched(s, h->aux, h->ev, e->cd, e->host.data(), z, e->prec,
                                      e->step_panels, &e->tb);
   if (he == hipSuccess)
-    he = bd::launch_brownian_batched(s, e->cd, z, max_n, step, e->trmv_prefix, e->trmv_blocks);
+    he = bd::launch_brownian_batched(s, e->cd, z, max_n, step, e->trmv_prefix, e->trmv_blocks,
+                                     d_step);
   if (he == hipSuccess) he = bd::launch_predictor_batched(s, e->cd, z, e->max_beads);
   if (he == hipSuccess)
     he = bd::launch_constrain_batched(s, e->cd, z, e->max_beads, e->mv_prefix, e->mv_blocks,
-                                      e->newton_maxit, e->st, e->host_st, &e->pairs_hint);
+                                      e->newton_maxit, e->st, e->host_st, &e->pairs_hint, budget);
   if (he == hipSuccess) {
     BD_LAUNCH("commit_positions_batched", commit_positions_batched_kernel,
               dim3((unsigned)((max_n + 255) / 256), 1, z), dim3(256), 0, s, e->cd);
     he = hipGetLastError();
   }
-  return hip_status(he);
+  if (he == hipSuccess && d_step) {
+    BD_LAUNCH("advance_step", set_step_kernel, dim3(1), dim3(1), 0, s,
+              const_cast<int64_t*>(d_step), (int64_t)0, 1);
+    he = hipGetLastError();
+  }
+  return he;
+}
+
+bd_status_t bd_ensemble_step(bd_ensemble_t e, int64_t step) {
+  if (!e) return BD_ERR_PARAM;
+  bd_handle_t h = e->h;
+  CallScope scope(h);
+  bd_status_t err = enter(h);
+  if (err != BD_OK) return err;
+  if (!e->gexec) return hip_status(ensemble_step_launches(e, h->stream, step, nullptr, 0));
+  // replay the captured step; its noise counter lives on the device
+  if (step != e->next_step) {
+    BD_LAUNCH("set_step", set_step_kernel, dim3(1), dim3(1), 0, h->stream, e->d_step, step, 0);
+    if (hipGetLastError() != hipSuccess) return BD_ERR_HIP;
+  }
+  if (hipGraphLaunch(e->gexec, h->stream) != hipSuccess) return BD_ERR_HIP;
+  e->next_step = step + 1;
+  return BD_OK;
+}
+
+bd_status_t bd_ensemble_capture(bd_ensemble_t e, int32_t max_products) {
+  if (!e || max_products < 0) return BD_ERR_PARAM;
+  bd_handle_t h = e->h;
+  if (h->prof_on) return BD_ERR_PARAM;  // the profiler's events stay out of graphs
+  bd_status_t err = enter(h);
+  if (err != BD_OK) return err;
+  const int budget = max_products > 0 ? max_products
+                     : e->pairs_hint > 0 ? e->pairs_hint + e->pairs_hint / 4 + 4
+                                         : 2 * 62;
+  if (!e->d_step && hipMalloc(&e->d_step, sizeof(int64_t)) != hipSuccess) return BD_ERR_ALLOC;
+  if (!e->cap && hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking) != hipSuccess)
+    return BD_ERR_HIP;
+  // the captured sequence starts after the work already queued on the
+  // handle's stream
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return BD_ERR_HIP;
+  if (hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return BD_ERR_HIP;
+  const hipError_t he = ensemble_step_launches(e, e->cap, 0, e->d_step, budget);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(e->cap, &g);
+  if (he != hipSuccess || ee != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return BD_ERR_HIP;
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return BD_ERR_HIP;
+  if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+  e->gexec = x;
+  e->budget = budget;
+  e->next_step = -1;  // the counter is set at the first replay
+  return BD_OK;
 }
 
 bd_status_t bd_ensemble_get_info(bd_ensemble_t e, bd_info_t* out) {

@@ -126,10 +126,14 @@ __global__ __launch_bounds__(256) void predictor_kernel(const double* __restrict
 }
 
 // Ensembles: chain blockIdx.z of the table; grids cover the largest chain.
+// d_step non-null: the noise counter from device memory (a captured step
+// replays with the plan's counter).
 __global__ __launch_bounds__(256) void noise_batched_kernel(const ChainDesc* __restrict__ cd,
-                                                             uint64_t step) {
+                                                             uint64_t step,
+                                                             const int64_t* __restrict__ d_step) {
   const ChainDesc& c = cd[blockIdx.z];
-  noise_body(blockIdx.x, c.xi, c.n, c.seed, c.chain_id, step, c.uniform);
+  const uint64_t st = d_step ? (uint64_t)*d_step : step;
+  noise_body(blockIdx.x, c.xi, c.n, c.seed, c.chain_id, st, c.uniform);
 }
 
 // one flattened grid: chain c owns trmv_batched_blocks(n_c) tiles
@@ -303,10 +307,11 @@ int trmv_batched_blocks(int64_t n) {
 }
 
 hipError_t launch_brownian_batched(hipStream_t s, const ChainDesc* cd, int count, int64_t max_n,
-                                   int64_t step, const int32_t* tile_prefix, int tile_blocks) {
+                                   int64_t step, const int32_t* tile_prefix, int tile_blocks,
+                                   const int64_t* d_step) {
   const int64_t nblk = (max_n + 3) / 4;
   BD_LAUNCH("noise_batched", noise_batched_kernel,
-            dim3((unsigned)((nblk + 255) / 256), 1, count), dim3(256), 0, s, cd, (uint64_t)step);
+            dim3((unsigned)((nblk + 255) / 256), 1, count), dim3(256), 0, s, cd, (uint64_t)step, d_step);
   BD_LAUNCH("trmv_tile_batched", trmv_tile_batched_kernel, dim3((unsigned)tile_blocks),
             dim3(kTv), 0, s, cd, tile_prefix, count);
   BD_LAUNCH("trmv_reduce_batched", trmv_reduce_batched_kernel,

@@ -190,7 +190,8 @@ int trmv_batched_blocks(int64_t n);
 hipError_t launch_rpy_assemble_batched(hipStream_t s, const ChainDesc* cd, int count,
                                        const int32_t* prefix, int blocks);
 hipError_t launch_brownian_batched(hipStream_t s, const ChainDesc* cd, int count, int64_t max_n,
-                                   int64_t step, const int32_t* tile_prefix, int tile_blocks);
+                                   int64_t step, const int32_t* tile_prefix, int tile_blocks,
+                                   const int64_t* d_step = nullptr);
 hipError_t launch_predictor_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads);
 // Runs the tension solve of every chain; returns once every chain's
 // iteration has finished (polls the `count` states at `st`, which are
@@ -198,8 +199,11 @@ hipError_t launch_predictor_batched(hipStream_t s, const ChainDesc* cd, int coun
 // mv_prefix: workgroups of the matrix-free product per chain, flattened
 // (constrain_mv_blocks(N) for chain c of the table), mv_blocks in all.
 int constrain_mv_blocks(int n_beads);
+// budget > 0: exactly `budget` (product, controller) pairs, no host round
+// trip (a chain not finished by then reports BD_ERR_NO_CONVERGE); 0: polled.
 hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads,
                                     const int32_t* mv_prefix, int mv_blocks, int newton_maxit,
-                                    DevState* st, DevState* host_states, int* pairs_hint);
+                                    DevState* st, DevState* host_states, int* pairs_hint,
+                                    int budget = 0);
 
 }  // namespace bd

@@ -1259,7 +1259,8 @@ hipError_t launch_dmatvec(hipStream_t s, const bd_params_t& p, const double* x, 
 
 hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads,
                                     const int32_t* mv_prefix, int mv_blocks, int newton_maxit,
-                                    DevState* st, DevState* host_states, int* pairs_hint) {
+                                    DevState* st, DevState* host_states, int* pairs_hint,
+                                    int budget) {
   const int M = max_beads - 1;
   int iblk = (M + 255) / 256;
   if (iblk < 16) iblk = 16;
@@ -1268,6 +1269,19 @@ hipError_t launch_constrain_batched(hipStream_t s, const ChainDesc* cd, int coun
   BD_LAUNCH("newton_controller_batched", newton_controller_batched_kernel, dim3(1, 1, count),
             dim3(kCtlThreads), 0, s, cd);
   const dim3 mvgrid(mv_blocks);
+  if (budget > 0) {
+    // a fixed number of pairs, asynchronous (capturable); launches for a
+    // finished chain return at once
+    for (int q = 0; q < budget; ++q) {
+      BD_LAUNCH("dmatvec_batched", dmatvec_batched_kernel, mvgrid, dim3(kMvThreads / 2), 0, s, cd,
+                mv_prefix, count);
+      BD_LAUNCH("newton_controller_batched", newton_controller_batched_kernel, dim3(1, 1, count),
+                dim3(kCtlThreads), 0, s, cd);
+    }
+    BD_LAUNCH("constrain_unfinished", constrain_unfinished_kernel, dim3((count + 63) / 64),
+              dim3(64), 0, s, st, count);
+    return hipGetLastError();
+  }
   // As for one chain: (matvec, controller) pairs in batches, the first sized
   // from the previous call, until every chain's iteration has finished;
   // launches for a finished chain return at once.

@@ -232,3 +232,28 @@ def test_ensemble_full_size(h, h_wide, prec, tol):
     print(f"ensemble prec {prec}: 3 steps, sampled chains {sampled}, worst |dr|/b vs oracle "
           f"{worst:.3e}", flush=True)
     ens.close()
+
+
+@pytest.mark.parametrize("prec", [B.PREC_FP64, B.PREC_MIXED])
+def test_captured_ensemble_step_replays_bitwise(h, prec):
+    # one step captured in a HIP graph (bd_ensemble_capture), replayed step
+    # after step, against a second plan of the same chains stepping with
+    # plain launches in between; a jump of the step counter resets the
+    # device counter
+    chains = _chains(SIZES)
+    xa, xb = _packed(chains), _packed(chains)
+    params = [pg for pg, _, _ in chains]
+    plain = B.Ensemble(h, params, xa, prec)
+    graph = B.Ensemble(h, params, xb, prec)
+    plain.step(0)
+    graph.step(0)  # a plain step first: its product count sizes the budget
+    graph.capture()
+    for s in (1, 2, 3, 7, 8):
+        plain.step(s)
+        graph.step(s)
+        ia, ib = plain.info(), graph.info()
+        assert all(i["status"] == B.OK for i in ib), (s, ib)
+        assert ia == ib, s
+        assert torch.equal(xa, xb), (prec, s, (xa - xb).abs().max().item())
+    plain.close()
+    graph.close()
