@@ -107,14 +107,26 @@ def syrk_launches(n: int, nb: int = 128, max_panels: int = 4, wide_rows: int = 4
     return out
 
 
-def syrk_per_launch(n: int, esize: int, kind: str = "bulk") -> tuple[float, float, int]:
-    """Average algorithmic flops and HBM bytes per trailing-update launch of
-    one kind, and the launch count, of one factorisation.  Bytes: each
-    updated lower element of C read and written once in FP64 (16 B) plus
-    each operand row of L read once (kdim values of `esize` bytes)."""
+def schedule_in_use(tuning: dict | None, n: int, prec: int) -> tuple[int, int]:
+    """(step panels, wide rows) that the library applies to an order-n
+    factorisation: the first row of the handle's schedule table with this
+    precision and n <= n_max, else the handle's defaults (environment)."""
+    for r in (tuning or {}).get("schedules", []):
+        if r["prec"] == prec and n <= r["n_max"]:
+            return int(r["step_panels"]), int(r["wide_rows"])
     sp = os.environ.get("BDRPY_STEP_PANELS", "")
     mp = 1 if sp.startswith("1") else 2 if sp.startswith("2") else 4
-    wide = int(os.environ.get("BDRPY_WIDE_ROWS", "4096"))
+    return mp, int(os.environ.get("BDRPY_WIDE_ROWS", "4096"))
+
+
+def syrk_per_launch(n: int, esize: int, kind: str = "bulk",
+                    schedule: tuple[int, int] | None = None) -> tuple[float, float, int]:
+    """Average algorithmic flops and HBM bytes per trailing-update launch of
+    one kind, and the launch count, of one factorisation in the schedule
+    (step panels, wide rows).  Bytes: each updated lower element of C read
+    and written once in FP64 (16 B) plus each operand row of L read once
+    (kdim values of `esize` bytes)."""
+    mp, wide = schedule if schedule is not None else schedule_in_use(None, n, -1)
     la = not os.environ.get("BDRPY_LOOKAHEAD", "").startswith("0")
     ls = [x for x in syrk_launches(n, max_panels=mp, wide_rows=wide, lookahead=la)
           if x[4] == kind]
@@ -164,25 +176,27 @@ def _records(prefix: str, paths):
     return out
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, schedule: tuple[int, int]):
     """HBM bytes per launch of `kernel` from the committed counter summaries
-    (profiles/*_traffic.md), or None when there is none or the kernel source
-    changed since."""
+    (profiles/*_traffic.md), or None when there is none, the kernel source
+    changed since or it was measured under another factorisation schedule
+    (step panels, wide rows): the average launch depends on it."""
     import glob
     for rec in _records("traffic_record: ", sorted(glob.glob(os.path.join(PROFILES, "*_traffic.md")))):
-        if rec.get("kernel") == kernel:
+        if rec.get("kernel") == kernel and rec.get("schedule") == list(schedule):
             return float(rec["hbm_bytes_per_launch"])
     return None
 
 
-def measured_mfma(kernel: str):
+def measured_mfma(kernel: str, schedule: tuple[int, int]):
     """Matrix-core counters of `kernel` (syrk_update_f32 / _f64) from the
-    committed summary, or None."""
+    committed summary, or None (as for measured_traffic)."""
     name = {"syrk_update_f32": "syrk_update_kernel<float, 128>",
             "syrk_update_f64": "syrk_update_kernel<double, 128>"}.get(kernel)
+    prec = "mixed" if kernel.endswith("f32") else "fp64"
     for rec in _records("mfma_record: ", [MFMA_RECORD]):
         k = rec.get("kernels", {}).get(name)
-        if k:
+        if k and rec.get("schedules", {}).get(prec) == list(schedule):
             return {"mfma_busy_frac": k["mfma_busy_frac"],
                     "mfma_flops_per_dispatch": k["mfma_flops_per_dispatch"],
                     "source": "profiles/cholesky_mfma_counters_n12288.md"}
@@ -548,8 +562,9 @@ def main() -> int:
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
         if kern.startswith("syrk_update"):
             f32 = kern.endswith("f32")
-            fl, by, cnt = syrk_per_launch(n, 4 if f32 else 8)
-            assert launches == cnt * args.profile_steps, (launches, cnt)
+            sched = schedule_in_use(h.tuning, n, pr)
+            fl, by, cnt = syrk_per_launch(n, 4 if f32 else 8, schedule=sched)
+            assert launches == cnt * args.profile_steps, (launches, cnt, sched)
             avg_s = kms * 1e-3 / launches
             peak_fl = PEAK_FP32 if f32 else PEAK_FP64
             # roofline: HBM-bound when the intensity is below the ridge point
@@ -558,8 +573,9 @@ def main() -> int:
             else:
                 achieved, peak, unit, bound = fl / avg_s / 1e12, peak_fl, "TFLOP/s", "mfma"
             rf = {"bound": bound, "kernel": kern, "achieved": achieved, "peak": peak,
-                  "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(kern),
-                  "mfma_counters": measured_mfma(kern),
+                  "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(kern, sched),
+                  "mfma_counters": measured_mfma(kern, sched),
+                  "schedule": {"step_panels": sched[0], "wide_rows": sched[1]},
                   "cholesky_frac_of_peak": result[prec_name].get("cholesky_frac_of_peak"),
                   "algorithmic_flops_per_launch": fl, "algorithmic_bytes_per_launch": by,
                   "intensity_flop_per_byte": fl / by,
