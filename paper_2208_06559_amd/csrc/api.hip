@@ -816,7 +816,7 @@ static bd_status_t ensemble_create_impl(bd_handle_t h, int32_t n_chains, const b
     if (prec == BD_PREC_MIXED) {
       char* pc = base + L.chol + bd::align_up(sizeof(double) * bd::kNB * bd::kNB, 256);
       d.P32[0] = reinterpret_cast<float*>(pc);
-      d.P32[1] = reinterpret_cast<float*>(pc + bd::align_up(sizeof(float) * (size_t)n * bd::kMaxStep, 256));
+      d.P32[1] = reinterpret_cast<float*>(pc + bd::p32_copy_bytes(n));
     }
     d.xi = reinterpret_cast<double*>(base + L.brown);
     d.part = reinterpret_cast<double*>(base + L.brown + bd::align_up(sizeof(double) * n, 256));

@@ -942,12 +942,17 @@ __global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
 //    for the columns on the lookahead chain) of the m x m trailing matrix; L
 //    is m x kdim (column-major, ldl) in FP64 or FP32, kdim a multiple of KC
 //    (one to four panels).  Four waves, each a TS/2 x TS/2 quadrant (the
-//    strictly upper quadrant of a diagonal tile is skipped).  Operands are
-//    staged through double-buffered LDS in K-chunks of KC, each row's KC
-//    values contiguous (rows 144 bytes apart: 16-byte accesses by 16
-//    consecutive rows meet every bank once).  Lane (lr, lk) of an MFMA takes
-//    k = (KC/4) lk + kq at step kq (one K order for both operands), so its
-//    operands for a whole chunk are one 32-byte run per 16 x 16 block.
+//    strictly upper quadrant of a diagonal tile is skipped).
+//    Operands go from HBM straight into LDS (global_load_lds, 16 bytes per
+//    lane, no registers), double-buffered in K-chunks of KC: each chunk's
+//    loads are issued after the current chunk's LDS reads and complete
+//    under its MFMAs.  LDS holds each operand k-major, [k][TS]: the global
+//    column segments land contiguously.  Within a quadrant, 16 x 16 block b
+//    of NBK = TS/32 takes the rows (columns) NBK i + b, so lane lr reads its
+//    NBK consecutive rows at one k in one access, one operand for each
+//    block; lane (lr, lk) takes k = 4 kq + lk at step kq for both operands.
+//    The row permutation makes each lane's outputs NBK consecutive rows of
+//    one column: C is read and written in 16-byte accesses.
 // ------------------------------------------------------------------------
 template <typename T>
 struct SyrkCfg;
@@ -962,35 +967,48 @@ struct SyrkCfg<float> {
   typedef f4 acc_t;
 };
 
-// LDS row of a staged operand chunk: KC values plus 16 bytes of padding
-template <typename T>
-constexpr int lds_row() { return SyrkCfg<T>::KC + 16 / (int)sizeof(T); }
-
 // Tile sets of one trailing update: every lower tile, only the first nnext
 // tile columns (the next step's panels, updated ahead), or every lower tile
 // outside those columns.
 enum { kTilesAll = 0, kTilesNext = 1, kTilesRest = 2 };
 
-// Pipeline: operand chunks of KC columns go global -> registers two chunks
-// ahead and registers -> LDS one chunk ahead (LDS double buffer); the C tile
-// is read in the epilogue.  Registers and LDS are sized for two workgroups
-// per CU, so one workgroup's loads and stores overlap the other's MFMAs.
-template <typename T, int TS>
+// W bytes of each lane from global memory straight into LDS, at the
+// wave-uniform address `lds` plus W times the lane index.
+template <int W>
+__device__ __forceinline__ void load_to_lds(const void* g, void* lds) {
+  static_assert(W == 16 || W == 4, "load width");
+  if constexpr (W == 16)
+    __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds(g, lds, 4, 0, 0);
+}
+
+// AL: the operand L and the matrix C start on 16-byte boundaries and their
+// column strides are multiples of 16 bytes.  Then each lane moves 16 bytes
+// per operand load and C is accessed in 16-byte vectors; otherwise 4 bytes
+// per load and scalar C accesses.  A 16-byte operand load may run up to 12
+// bytes past a column's last row m - 1 (the group holding it); past the
+// last column of an FP32 panel copy that needs the slack of kP32Tail.
+template <typename T, int TS, bool AL>
 __device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, int64_t ld,
                                                  const T* __restrict__ L, int64_t ldl, int64_t m,
                                                  int kdim, int tiles, int nnext) {
   constexpr int KC = SyrkCfg<T>::KC;
   typedef typename SyrkCfg<T>::acc_t acc_t;
-  constexpr int WT = TS / 2;           // each wave owns a WT x WT quadrant
-  constexpr int NBK = WT / 16;         // 16 x 16 MFMA blocks per quadrant side
-  constexpr int NLD = KC * TS / 256;   // elements per thread per operand per chunk
+  constexpr int WT = TS / 2;    // each wave owns a WT x WT quadrant
+  constexpr int NBK = WT / 16;  // 16 x 16 MFMA blocks per quadrant side
+  constexpr int KQ = KC / 4;    // MFMA steps per chunk
+  constexpr int SZ = (int)sizeof(T);
+  constexpr int W = AL ? 16 : 4;                // bytes per lane per load
+  constexpr int RB = TS * SZ;                   // bytes per LDS k-row
+  constexpr int BI = 64 * W;                    // bytes per load instruction
+  constexpr int NIW = KC * RB / BI / 4;         // loads per wave per operand per chunk
   static_assert(TS == 64 || TS == 128, "tile size");
+  static_assert(NIW >= 1 && NIW * BI * 4 == KC * RB, "load split");
+  static_assert(BI % RB == 0 || RB % BI == 0, "load shape");
   if constexpr (TS == 64) __builtin_amdgcn_s_setprio(3);  // the lookahead chain's updates
-  constexpr int LR = lds_row<T>();
-  constexpr int KQ = KC / 4;  // MFMA steps per chunk; each lane's run of k values
-  static_assert(KQ * sizeof(T) == 32 && NLD * sizeof(T) % 16 == 0, "32-byte runs");
-  __shared__ __attribute__((aligned(16))) T As[2][TS][LR];  // row side, [row][k]
-  __shared__ __attribute__((aligned(16))) T Bs[2][TS][LR];  // column side
+  __shared__ __attribute__((aligned(16))) T As[2][KC][TS];  // row side
+  __shared__ __attribute__((aligned(16))) T Bs[2][KC][TS];  // column side
 
   int ti, tj;
   if (tiles == kTilesNext) {
@@ -1013,7 +1031,8 @@ __device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, 
   }
   const int64_t row0 = (int64_t)ti * TS, col0 = (int64_t)tj * TS;
   const int tid = threadIdx.x;
-  const int w = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int wr = w >> 1, wc = w & 1;
   const bool active = !(ti == tj && wr < wc);
 
@@ -1025,77 +1044,98 @@ __device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[bj][bi][r] = 0;
 
-  // thread: operand row gr, chunk columns gk .. gk + NLD - 1 (consecutive
-  // lanes read consecutive rows of one column)
-  const int gr = tid % TS, gk = (tid / TS) * NLD;
-  // rows past m are clamped (their products only reach masked outputs)
-  const int64_t ia = (row0 + gr < m) ? row0 + gr : m - 1;
-  const int64_t ib = (col0 + gr < m) ? col0 + gr : m - 1;
-  T ra[NLD], rb[NLD];
-  auto gload = [&](int kk) {
+  // Loads: instruction u of wave w fills bytes [BI (w NIW + u), + BI) of an
+  // operand's chunk buffer, lane l the W bytes at W l within them: k-row
+  // kr, byte eb of that row, i.e. global row r0 + eb / SZ of column kk + kr.
+  // A lane whose group starts at or past m reads the tile's first row
+  // instead (in bounds; such rows only reach masked outputs).
+  const char* __restrict__ Lb = reinterpret_cast<const char*>(L);
+  const int64_t ldb = ldl * SZ;  // column stride in bytes
+  auto src = [&](int64_t r0b, int u, int kk) {
+    const int B = BI * (w * NIW + u) + W * lane;
+    const int kr = B / RB, eb = B % RB;
+    const int64_t rb = (r0b + eb < m * SZ) ? r0b + eb : r0b + eb % SZ;
+    return Lb + (int64_t)(kk + kr) * ldb + rb;
+  };
+  auto dma = [&](int buf, int kk) {
 #pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-      ra[q] = L[(int64_t)(kk + gk + q) * ldl + ia];
-      rb[q] = L[(int64_t)(kk + gk + q) * ldl + ib];
+    for (int u = 0; u < NIW; ++u) {
+      char* da = reinterpret_cast<char*>(&As[buf][0][0]) + BI * (w * NIW + u);
+      char* db = reinterpret_cast<char*>(&Bs[buf][0][0]) + BI * (w * NIW + u);
+      load_to_lds<W>(src(row0 * SZ, u, kk), da);
+      load_to_lds<W>(src(col0 * SZ, u, kk), db);
     }
   };
-  typedef T v16 __attribute__((ext_vector_type(16 / sizeof(T))));
-  constexpr int V = 16 / (int)sizeof(T);  // values per 16-byte access
-  auto sstore = [&](int buf) {
+  typedef T vn __attribute__((ext_vector_type(NBK)));
+  auto chunk = [&](int buf) {
+    vn af[KQ], bf[KQ];
 #pragma unroll
-    for (int q = 0; q < NLD; q += V) {
-      v16 a, b;
-#pragma unroll
-      for (int u = 0; u < V; ++u) {
-        a[u] = ra[q + u];
-        b[u] = rb[q + u];
-      }
-      *reinterpret_cast<v16*>(&As[buf][gr][gk + q]) = a;
-      *reinterpret_cast<v16*>(&Bs[buf][gr][gk + q]) = b;
+    for (int kq = 0; kq < KQ; ++kq) {
+      af[kq] = *reinterpret_cast<const vn*>(&Bs[buf][4 * kq + lk][WT * wc + NBK * lr]);
+      bf[kq] = *reinterpret_cast<const vn*>(&As[buf][4 * kq + lk][WT * wr + NBK * lr]);
     }
-  };
-
-  const int nch = kdim / KC;
-  gload(0);
-  sstore(0);
-  if (nch > 1) gload(KC);
-  __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1;
-    if (active) {
-      T af[NBK][KQ], bf[NBK][KQ];
-#pragma unroll
-      for (int bj = 0; bj < NBK; ++bj)
-#pragma unroll
-        for (int h = 0; h < KQ; h += V) {
-          const v16 x = *reinterpret_cast<const v16*>(&Bs[buf][WT * wc + 16 * bj + lr][KQ * lk + h]);
-#pragma unroll
-          for (int u = 0; u < V; ++u) af[bj][h + u] = x[u];
-        }
-#pragma unroll
-      for (int bi = 0; bi < NBK; ++bi)
-#pragma unroll
-        for (int h = 0; h < KQ; h += V) {
-          const v16 x = *reinterpret_cast<const v16*>(&As[buf][WT * wr + 16 * bi + lr][KQ * lk + h]);
-#pragma unroll
-          for (int u = 0; u < V; ++u) bf[bi][h + u] = x[u];
-        }
+    return [=](acc_t (&a)[NBK][NBK]) {
 #pragma unroll
       for (int kq = 0; kq < KQ; ++kq)
 #pragma unroll
         for (int bj = 0; bj < NBK; ++bj)
 #pragma unroll
-          for (int bi = 0; bi < NBK; ++bi) acc[bj][bi] = mfma(af[bj][kq], bf[bi][kq], acc[bj][bi]);
-    }
-    if (ch + 1 < nch) {
-      sstore(buf ^ 1);                       // chunk ch+1, loaded one iteration ago
-      if (ch + 2 < nch) gload((ch + 2) * KC);  // two chunks ahead
+          for (int bi = 0; bi < NBK; ++bi) a[bj][bi] = mfma(af[kq][bj], bf[kq][bi], a[bj][bi]);
+    };
+  };
+
+  const int nch = kdim / KC;
+  dma(0, 0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (active) {
+      auto run = chunk(buf);
+      __builtin_amdgcn_sched_barrier(0);  // the LDS reads go out before the next loads
+      if (ch + 1 < nch) dma(buf ^ 1, (ch + 1) * KC);
+      run(acc);
+    } else if (ch + 1 < nch) {
+      dma(buf ^ 1, (ch + 1) * KC);
     }
     __syncthreads();
   }
   if (!active) return;
-  // C is read here, one 16-value batch per column block: with two
-  // workgroups per CU its latency overlaps the other workgroup's MFMA work
+
+  // Epilogue.  Output (bj, bi, r) of lane (lr, lk) is C(i, j) with
+  // i = qi + NBK lr + bi and j = qj + NBK res_row(lk, r) + bj: for fixed
+  // (bj, r) a lane holds NBK consecutive rows of one column.
+  const int64_t qi = row0 + WT * wr, qj = col0 + WT * wc;
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  if (AL && qi + WT <= m && qi >= qj + WT - 1) {  // whole quadrant inside, on or below the diagonal
+    double* __restrict__ Cl = C + qj * ld + qi + NBK * lr;
+    constexpr int EB = NBK / 2;  // column blocks per batch
+#pragma unroll
+    for (int b0 = 0; b0 < NBK; b0 += EB) {
+      d2v cv[EB][4][NBK / 2];
+#pragma unroll
+      for (int e = 0; e < EB; ++e)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double* cc = Cl + (int64_t)(NBK * res_row(acc[0][0], lk, r) + b0 + e) * ld;
+#pragma unroll
+          for (int h = 0; h < NBK / 2; ++h) cv[e][r][h] = *reinterpret_cast<const d2v*>(cc + 2 * h);
+        }
+#pragma unroll
+      for (int e = 0; e < EB; ++e)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double* cc = Cl + (int64_t)(NBK * res_row(acc[0][0], lk, r) + b0 + e) * ld;
+#pragma unroll
+          for (int h = 0; h < NBK / 2; ++h) {
+            d2v v = cv[e][r][h];
+            v[0] -= (double)acc[b0 + e][2 * h][r];
+            v[1] -= (double)acc[b0 + e][2 * h + 1][r];
+            *reinterpret_cast<d2v*>(cc + 2 * h) = v;
+          }
+        }
+    }
+    return;
+  }
 #pragma unroll
   for (int bj = 0; bj < NBK; ++bj) {
     double cv[NBK][4];
@@ -1103,16 +1143,16 @@ __device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, 
     for (int bi = 0; bi < NBK; ++bi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = row0 + WT * wr + 16 * bi + lr;
-        const int64_t j = col0 + WT * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
+        const int64_t i = qi + NBK * lr + bi;
+        const int64_t j = qj + NBK * res_row(acc[bj][bi], lk, r) + bj;
         cv[bi][r] = (i < m && j < m && i >= j) ? C[j * ld + i] : 0.0;
       }
 #pragma unroll
     for (int bi = 0; bi < NBK; ++bi)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = row0 + WT * wr + 16 * bi + lr;
-        const int64_t j = col0 + WT * wc + 16 * bj + res_row(acc[bj][bi], lk, r);
+        const int64_t i = qi + NBK * lr + bi;
+        const int64_t j = qj + NBK * res_row(acc[bj][bi], lk, r) + bj;
         if (i < m && j < m && i >= j) C[j * ld + i] = cv[bi][r] - (double)acc[bj][bi][r];
       }
   }
@@ -1120,12 +1160,12 @@ __device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, 
 
 // XCD x receives workgroups x, x+8, ...: cnt(x) = base + (x < rem) of them;
 // the q-th of them takes tile x*base + min(x, rem) + q (a bijection).
-template <typename T, int TS>
+template <typename T, int TS, bool AL>
 __global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict__ C, int64_t ld,
                                                               const T* __restrict__ L, int64_t ldl,
                                                               int64_t m, int kdim, int tiles,
                                                               int nnext) {
-  syrk_update_body<T, TS>(xcd_contiguous(blockIdx.x, gridDim.x), C, ld, L, ldl, m, kdim, tiles,
+  syrk_update_body<T, TS, AL>(xcd_contiguous(blockIdx.x, gridDim.x), C, ld, L, ldl, m, kdim, tiles,
                           nnext);
 }
 
@@ -1152,8 +1192,8 @@ __global__ __launch_bounds__(kPsThreads) void panel_solve_batched_kernel(
   const ChainDesc& c = cd[ci];
   const int64_t m = c.n - kp - NB;
   float* P = c.P32[pidx];
-  if (P) P += (kp - k0) * c.n + kp + NB;
-  panel_solve_body(blockIdx.x - prefix[ci], c.D, c.ld, kp, NB, m, c.W, P, c.n);
+  if (P) P += (kp - k0) * p32_ld(c.n) + kp + NB;
+  panel_solve_body(blockIdx.x - prefix[ci], c.D, c.ld, kp, NB, m, c.W, P, p32_ld(c.n));
 }
 
 // Tiles of tile set `tiles` in an m x m trailing matrix with TS x TS tiles;
@@ -1180,7 +1220,7 @@ __host__ __device__ inline int64_t syrk_tile_count(int64_t m, int ts, int tiles,
 // step (the tile columns updated ahead).
 // One flattened grid over every chain's tiles, each XCD taking a contiguous
 // range of (chain, tile).
-template <typename T, int TS>
+template <typename T, int TS, bool AL>
 __global__ __launch_bounds__(256, 2) void syrk_update_batched_kernel(
     const ChainDesc* __restrict__ cd, const int32_t* __restrict__ prefix, int z, int64_t k0,
     int64_t r0, int kdim, int tiles, int nnext_panels, int pidx) {
@@ -1195,25 +1235,25 @@ __global__ __launch_bounds__(256, 2) void syrk_update_batched_kernel(
   int64_t ldl;
   if constexpr (sizeof(T) == 4) {
     L = c.P32[pidx] + r0;
-    ldl = c.n;
+    ldl = p32_ld(c.n);
   } else {
     L = c.D + k0 * c.ld + r0;
     ldl = c.ld;
   }
-  syrk_update_body<T, TS>(t, c.D + r0 * c.ld + r0, c.ld, L, ldl, m, kdim, tiles, (int)nnext);
+  syrk_update_body<T, TS, AL>(t, c.D + r0 * c.ld + r0, c.ld, L, ldl, m, kdim, tiles, (int)nnext);
 }
 
 }  // namespace
 
 size_t cholesky_batched_workspace_bytes(int64_t n, bd_precision_t prec) {
   size_t b = align_up(sizeof(double) * NB * NB, 256);
-  if (prec == BD_PREC_MIXED) b += 2 * align_up(sizeof(float) * (size_t)n * kMaxStep, 256);
+  if (prec == BD_PREC_MIXED) b += 2 * p32_copy_bytes(n);
   return b;
 }
 
 size_t cholesky_workspace_bytes(int64_t n, bd_precision_t prec) {
   size_t b = align_up(sizeof(double) * NB * NB, 256);  // four 32 x 32 inverses (NB*NB/4 used)
-  if (prec == BD_PREC_MIXED) b += 2 * align_up(sizeof(float) * (size_t)n * kMaxStep, 256);
+  if (prec == BD_PREC_MIXED) b += 2 * p32_copy_bytes(n);
   return b;
 }
 
@@ -1266,11 +1306,17 @@ hipError_t factor_panel(const CholCtx& c, hipStream_t s, int64_t k0, int64_t kp)
   const int64_t m = c.n - kp - nb;
   if (m > 0) {  // then nb == NB: only the last panel can be narrower
     float* P = step_copy(c, k0);
-    if (P) P += (kp - k0) * c.n + kp + NB;  // column kp - k0 of the step, row kp + NB
+    if (P) P += (kp - k0) * p32_ld(c.n) + kp + NB;  // column kp - k0 of the step, row kp + NB
     BD_LAUNCH("panel_solve", panel_solve_kernel, dim3((unsigned)((m + kRB - 1) / kRB)),
-              dim3(kPsThreads), 0, s, c.A, c.ld, kp, nb, m, c.W, P, c.n);
+              dim3(kPsThreads), 0, s, c.A, c.ld, kp, nb, m, c.W, P, p32_ld(c.n));
   }
   return hipGetLastError();
+}
+
+// A pointer and a column stride (bytes) that keep every column on a
+// 16-byte boundary.
+bool aligned16(const void* p, int64_t stride_bytes) {
+  return reinterpret_cast<uintptr_t>(p) % 16 == 0 && stride_bytes % 16 == 0;
 }
 
 // C -= L L^T on the trailing matrix from row/column r0 with the kdim columns
@@ -1294,18 +1340,35 @@ hipError_t trailing(const CholCtx& c, hipStream_t s, int64_t k0, int64_t r0, int
   const float* P = step_copy(c, k0);
   const double* L64 = c.A + k0 * c.ld + r0;
   const dim3 grid((unsigned)nt);
-  if (P && ts == kTS) {
-    BD_LAUNCH("syrk_update_f32", (syrk_update_kernel<float, kTS>), grid, dim3(256), 0, s, C, c.ld,
-              P + r0, c.n, m, kdim, tiles, nnext);
-  } else if (P) {
-    BD_LAUNCH("syrk_next_f32", (syrk_update_kernel<float, kTS / 2>), grid, dim3(256), 0, s, C,
-              c.ld, P + r0, c.n, m, kdim, tiles, nnext);
-  } else if (ts == kTS) {
-    BD_LAUNCH("syrk_update_f64", (syrk_update_kernel<double, kTS>), grid, dim3(256), 0, s, C,
-              c.ld, L64, c.ld, m, kdim, tiles, nnext);
+  if (P) {
+    const int64_t ldp = p32_ld(c.n);
+    const bool al = aligned16(P + r0, ldp * 4) && aligned16(C, c.ld * 8);
+    if (ts == kTS && al)
+      BD_LAUNCH("syrk_update_f32", (syrk_update_kernel<float, kTS, true>), grid, dim3(256), 0, s,
+                C, c.ld, P + r0, ldp, m, kdim, tiles, nnext);
+    else if (ts == kTS)
+      BD_LAUNCH("syrk_update_f32", (syrk_update_kernel<float, kTS, false>), grid, dim3(256), 0, s,
+                C, c.ld, P + r0, ldp, m, kdim, tiles, nnext);
+    else if (al)
+      BD_LAUNCH("syrk_next_f32", (syrk_update_kernel<float, kTS / 2, true>), grid, dim3(256), 0,
+                s, C, c.ld, P + r0, ldp, m, kdim, tiles, nnext);
+    else
+      BD_LAUNCH("syrk_next_f32", (syrk_update_kernel<float, kTS / 2, false>), grid, dim3(256), 0,
+                s, C, c.ld, P + r0, ldp, m, kdim, tiles, nnext);
   } else {
-    BD_LAUNCH("syrk_next_f64", (syrk_update_kernel<double, kTS / 2>), grid, dim3(256), 0, s, C,
-              c.ld, L64, c.ld, m, kdim, tiles, nnext);
+    const bool al = aligned16(L64, c.ld * 8) && aligned16(C, c.ld * 8);
+    if (ts == kTS && al)
+      BD_LAUNCH("syrk_update_f64", (syrk_update_kernel<double, kTS, true>), grid, dim3(256), 0, s,
+                C, c.ld, L64, c.ld, m, kdim, tiles, nnext);
+    else if (ts == kTS)
+      BD_LAUNCH("syrk_update_f64", (syrk_update_kernel<double, kTS, false>), grid, dim3(256), 0,
+                s, C, c.ld, L64, c.ld, m, kdim, tiles, nnext);
+    else if (al)
+      BD_LAUNCH("syrk_next_f64", (syrk_update_kernel<double, kTS / 2, true>), grid, dim3(256), 0,
+                s, C, c.ld, L64, c.ld, m, kdim, tiles, nnext);
+    else
+      BD_LAUNCH("syrk_next_f64", (syrk_update_kernel<double, kTS / 2, false>), grid, dim3(256), 0,
+                s, C, c.ld, L64, c.ld, m, kdim, tiles, nnext);
   }
   return hipGetLastError();
 }
@@ -1352,7 +1415,7 @@ hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int
   if (prec == BD_PREC_MIXED) {
     char* p = static_cast<char*>(ws) + align_up(sizeof(double) * NB * NB, 256);
     c.P32[0] = reinterpret_cast<float*>(p);
-    c.P32[1] = reinterpret_cast<float*>(p + align_up(sizeof(float) * (size_t)n * kMaxStep, 256));
+    c.P32[1] = reinterpret_cast<float*>(p + p32_copy_bytes(n));
   }
   hipError_t e;
   int64_t w = 0;
@@ -1451,18 +1514,32 @@ hipError_t batch_trailing(const BatchCtx& b, hipStream_t s, int64_t k0, int64_t 
   if (total == 0 || b.tb->record) return hipSuccess;
   const dim3 grid((unsigned)total);
   const int pidx = batch_pidx(b, k0);
+  // every chain's operand and matrix on 16-byte boundaries (the library's
+  // own layouts are; a caller's workspace might not be)
+  bool al = true;
+  for (int c = 0; c < z; ++c) {
+    const ChainDesc& h = b.host[c];
+    al = al && aligned16(h.D, h.ld * 8) &&
+         (!b.mixed || (aligned16(h.P32[0], p32_ld(h.n) * 4) && aligned16(h.P32[1], 16)));
+  }
+#define BD_SYRK_BATCHED(NAME, T, TSZ)                                                        \
+  do {                                                                                       \
+    if (al)                                                                                  \
+      BD_LAUNCH(NAME, (syrk_update_batched_kernel<T, TSZ, true>), grid, dim3(256), 0, s, b.cd, \
+                pre, z, k0, r0, kdim, tiles, nnext_panels, pidx);                            \
+    else                                                                                     \
+      BD_LAUNCH(NAME, (syrk_update_batched_kernel<T, TSZ, false>), grid, dim3(256), 0, s,      \
+                b.cd, pre, z, k0, r0, kdim, tiles, nnext_panels, pidx);                      \
+  } while (0)
   if (b.mixed && ts == kTS)
-    BD_LAUNCH("syrk_update_f32_batched", (syrk_update_batched_kernel<float, kTS>), grid, dim3(256),
-              0, s, b.cd, pre, z, k0, r0, kdim, tiles, nnext_panels, pidx);
+    BD_SYRK_BATCHED("syrk_update_f32_batched", float, kTS);
   else if (b.mixed)
-    BD_LAUNCH("syrk_next_f32_batched", (syrk_update_batched_kernel<float, kTS / 2>), grid,
-              dim3(256), 0, s, b.cd, pre, z, k0, r0, kdim, tiles, nnext_panels, pidx);
+    BD_SYRK_BATCHED("syrk_next_f32_batched", float, kTS / 2);
   else if (ts == kTS)
-    BD_LAUNCH("syrk_update_f64_batched", (syrk_update_batched_kernel<double, kTS>), grid,
-              dim3(256), 0, s, b.cd, pre, z, k0, r0, kdim, tiles, nnext_panels, pidx);
+    BD_SYRK_BATCHED("syrk_update_f64_batched", double, kTS);
   else
-    BD_LAUNCH("syrk_next_f64_batched", (syrk_update_batched_kernel<double, kTS / 2>), grid,
-              dim3(256), 0, s, b.cd, pre, z, k0, r0, kdim, tiles, nnext_panels, pidx);
+    BD_SYRK_BATCHED("syrk_next_f64_batched", double, kTS / 2);
+#undef BD_SYRK_BATCHED
   return hipGetLastError();
 }
 

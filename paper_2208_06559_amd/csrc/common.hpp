@@ -124,6 +124,15 @@ hipError_t launch_fraenkel_update(hipStream_t s, const bd_params_t& p, double K,
                                   const double* v, const double* y, DevState* st);
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+// One FP32 panel copy of the mixed-precision factorisation: n x kMaxStep
+// floats plus kP32Tail of slack, since the trailing update's 16-byte
+// operand loads may run up to three floats past a column's last row.
+constexpr int kP32Tail = 64;
+// Its column stride: n rounded up to 16 bytes, so that columns stay aligned.
+__host__ __device__ inline int64_t p32_ld(int64_t n) { return (n + 3) / 4 * 4; }
+__host__ __device__ inline size_t p32_copy_bytes(int64_t n) {
+  return align_up(sizeof(float) * ((size_t)p32_ld(n) * kMaxStep + kP32Tail), 256);
+}
 
 // ---------------------------------------------------------------- ensembles
 // One chain of an ensemble as the batched kernels see it: the chain's
@@ -144,7 +153,7 @@ struct ChainDesc {
   double* x;          // N x 3 positions (in the packed array of the ensemble)
   double* D;          // n x ld diffusion tensor, then its factor
   double* W;          // Cholesky: inverses of the diagonal sub-blocks
-  float* P32[2];      // Cholesky MIXED: FP32 panel copies of alternate steps (n x kMaxStep)
+  float* P32[2];      // Cholesky MIXED: FP32 panel copies of alternate steps (p32_ld(n) x kMaxStep)
   double* xi;         // noise (n)
   double* part;       // TRMV partial sums
   double* y;          // Brownian displacement (n)

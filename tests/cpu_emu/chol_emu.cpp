@@ -35,8 +35,12 @@ void fail(const char* what, int64_t a, int64_t b, int64_t c) {
 void observe(const void* kernel, dim3 grid, const int64_t* a, int nargs) {
   using namespace bd;
   int64_t ts = 0;
-  if (kernel == (const void*)&syrk_update_kernel<double, kTS>) ts = kTS;
-  if (kernel == (const void*)&syrk_update_kernel<double, kTS / 2>) ts = kTS / 2;
+  if (kernel == (const void*)&syrk_update_kernel<double, kTS, true> ||
+      kernel == (const void*)&syrk_update_kernel<double, kTS, false>)
+    ts = kTS;
+  if (kernel == (const void*)&syrk_update_kernel<double, kTS / 2, true> ||
+      kernel == (const void*)&syrk_update_kernel<double, kTS / 2, false>)
+    ts = kTS / 2;
   if (ts) {
     // (C, ld, L, ldl, m, kdim, tiles, nnext): tile size ts, nnext in tiles
     const int64_t coff = (a[0] - (int64_t)(uintptr_t)g_A) / 8, loff = (a[2] - (int64_t)(uintptr_t)g_A) / 8;

@@ -63,6 +63,12 @@ inline int atomicMin(int* p, int v) { const int o = *p; if (v < o) *p = v; retur
 #define __builtin_amdgcn_fence(...) ((void)0)
 #define __builtin_amdgcn_wave_barrier() ((void)0)
 #define __builtin_amdgcn_sched_barrier(m) ((void)0)
+#define __builtin_amdgcn_sched_group_barrier(m, n, i) ((void)0)
+// Load to LDS: each lane's `size` bytes from its global address land at
+// the wave-uniform LDS address plus offset plus lane * size.
+inline void __builtin_amdgcn_global_load_lds(const void* src, void* lds, unsigned size, int offset, int) {
+  memcpy(static_cast<char*>(lds) + offset + (threadIdx.x & 63) * size, src, size);
+}
 #define __builtin_amdgcn_s_barrier() ((void)0)
 #define __builtin_amdgcn_s_setprio(p) ((void)0)
 #define __builtin_amdgcn_s_sleep(n) ((void)0)
