@@ -1084,58 +1084,82 @@ __device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, 
     };
   };
 
+  // Epilogue addressing.  Output (bj, bi, r) of lane (lr, lk) is C(i, j)
+  // with i = qi + NBK lr + bi and j = qj + NBK res_row(lk, r) + bj: for
+  // fixed (bj, r) a lane holds NBK consecutive rows of one column.
+  const int64_t qi = row0 + WT * wr, qj = col0 + WT * wc;
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  // a quadrant wholly inside the matrix, on or below the diagonal, with C
+  // on 16-byte boundaries: C moves in 16-byte vectors, in batches of EB
+  // column blocks, the first batch read under the last chunk's products
+  // and each later one read while the previous one is written
+  const bool whole = AL && active && qi + WT <= m && qi >= qj + WT - 1;
+  double* __restrict__ Cl = C + qj * ld + qi + NBK * lr;
+  constexpr int EB = (sizeof(T) == 4) ? NBK / 2 : 1;
+  constexpr int NBT = NBK / EB;
+  typedef d2v batch_t[EB][4][NBK / 2];
+  auto cload = [&](int b0, batch_t& cv) {
+#pragma unroll
+    for (int e = 0; e < EB; ++e)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double* cc = Cl + (int64_t)(NBK * res_row(acc[0][0], lk, r) + b0 + e) * ld;
+#pragma unroll
+        for (int h = 0; h < NBK / 2; ++h) cv[e][r][h] = *reinterpret_cast<const d2v*>(cc + 2 * h);
+      }
+  };
+  auto cstore = [&](int b0, const batch_t& cv) {
+#pragma unroll
+    for (int e = 0; e < EB; ++e)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double* cc = Cl + (int64_t)(NBK * res_row(acc[0][0], lk, r) + b0 + e) * ld;
+#pragma unroll
+        for (int h = 0; h < NBK / 2; ++h) {
+          d2v v = cv[e][r][h];
+          v[0] -= (double)acc[b0 + e][2 * h][r];
+          v[1] -= (double)acc[b0 + e][2 * h + 1][r];
+          *reinterpret_cast<d2v*>(cc + 2 * h) = v;
+        }
+      }
+  };
+
   const int nch = kdim / KC;
   dma(0, 0);
   __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
+  for (int ch = 0; ch + 1 < nch; ++ch) {
     const int buf = ch & 1;
     if (active) {
       auto run = chunk(buf);
       __builtin_amdgcn_sched_barrier(0);  // the LDS reads go out before the next loads
-      if (ch + 1 < nch) dma(buf ^ 1, (ch + 1) * KC);
+      dma(buf ^ 1, (ch + 1) * KC);
       run(acc);
-    } else if (ch + 1 < nch) {
+    } else {
       dma(buf ^ 1, (ch + 1) * KC);
     }
     __syncthreads();
   }
   if (!active) return;
-
-  // Epilogue.  Output (bj, bi, r) of lane (lr, lk) is C(i, j) with
-  // i = qi + NBK lr + bi and j = qj + NBK res_row(lk, r) + bj: for fixed
-  // (bj, r) a lane holds NBK consecutive rows of one column.
-  const int64_t qi = row0 + WT * wr, qj = col0 + WT * wc;
-  typedef double d2v __attribute__((ext_vector_type(2)));
-  if (AL && qi + WT <= m && qi >= qj + WT - 1) {  // whole quadrant inside, on or below the diagonal
-    double* __restrict__ Cl = C + qj * ld + qi + NBK * lr;
-    constexpr int EB = NBK / 2;  // column blocks per batch
+  batch_t c0;
+  {
+    auto run = chunk((nch - 1) & 1);
+    if (whole) cload(0, c0);
+    run(acc);
+  }
+  if (whole) {
 #pragma unroll
-    for (int b0 = 0; b0 < NBK; b0 += EB) {
-      d2v cv[EB][4][NBK / 2];
-#pragma unroll
-      for (int e = 0; e < EB; ++e)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double* cc = Cl + (int64_t)(NBK * res_row(acc[0][0], lk, r) + b0 + e) * ld;
-#pragma unroll
-          for (int h = 0; h < NBK / 2; ++h) cv[e][r][h] = *reinterpret_cast<const d2v*>(cc + 2 * h);
-        }
-#pragma unroll
-      for (int e = 0; e < EB; ++e)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          double* cc = Cl + (int64_t)(NBK * res_row(acc[0][0], lk, r) + b0 + e) * ld;
-#pragma unroll
-          for (int h = 0; h < NBK / 2; ++h) {
-            d2v v = cv[e][r][h];
-            v[0] -= (double)acc[b0 + e][2 * h][r];
-            v[1] -= (double)acc[b0 + e][2 * h + 1][r];
-            *reinterpret_cast<d2v*>(cc + 2 * h) = v;
-          }
-        }
+    for (int bt = 0; bt < NBT; bt += 2) {
+      batch_t c1;
+      if (bt + 1 < NBT) cload((bt + 1) * EB, c1);
+      cstore(bt * EB, c0);
+      if (bt + 1 < NBT) {
+        if (bt + 2 < NBT) cload((bt + 2) * EB, c0);
+        cstore((bt + 1) * EB, c1);
+      }
     }
     return;
   }
+  // other quadrants: element by element, masked
 #pragma unroll
   for (int bj = 0; bj < NBK; ++bj) {
     double cv[NBK][4];
