@@ -191,8 +191,8 @@ def measured_traffic(kernel: str, schedule: tuple[int, int]):
 def measured_mfma(kernel: str, schedule: tuple[int, int]):
     """Matrix-core counters of `kernel` (syrk_update_f32 / _f64) from the
     committed summary, or None (as for measured_traffic)."""
-    name = {"syrk_update_f32": "syrk_update_kernel<float, 128>",
-            "syrk_update_f64": "syrk_update_kernel<double, 128>"}.get(kernel)
+    name = {"syrk_update_f32": "syrk_update_kernel<float, 128, true>",
+            "syrk_update_f64": "syrk_update_kernel<double, 128, true>"}.get(kernel)
     prec = "mixed" if kernel.endswith("f32") else "fp64"
     for rec in _records("mfma_record: ", [MFMA_RECORD]):
         k = rec.get("kernels", {}).get(name)
@@ -543,6 +543,45 @@ def main() -> int:
     torch.cuda.empty_cache()
 
     # ------------------------------------------- dominant-kernel roofline
+    def isolated_bulk(kern, pr, sched, f32):
+        """The same kernel with the lookahead stream off (every launch of
+        the factorisation in order on one stream, nothing beside it): its
+        average launch time over one step's factorisation, and the fraction
+        of peak that gives, beside the in-stream figure above (where the
+        diagonal blocks and panel solves of the next step share the GPU)."""
+        old = os.environ.get("BDRPY_LOOKAHEAD")
+        os.environ["BDRPY_LOOKAHEAD"] = "0"
+        try:
+            hs = B.Handle(0, tuned=True)
+        finally:
+            if old is None:
+                del os.environ["BDRPY_LOOKAHEAD"]
+            else:
+                os.environ["BDRPY_LOOKAHEAD"] = old
+        try:
+            xx = x0.clone()
+            wsp = hs.workspace(B.OP_STEP, n, pr)
+            hs.step(p, 0, xx, pr, wsp)
+            torch.cuda.synchronize()
+            hs.profile_begin()
+            hs.step(p, 1, xx, pr, wsp)
+            st = hs.profile_end()
+            if hs.info()["status"] != B.OK or kern not in st:
+                return None
+            launches, kms = st[kern]
+            ls = [x for x in syrk_launches(n, max_panels=sched[0], wide_rows=sched[1],
+                                           lookahead=False) if x[4] == "bulk"]
+            if launches != len(ls):
+                return None
+            fl = sum(x[0] for x in ls) / launches
+            peak_fl = PEAK_FP32 if f32 else PEAK_FP64
+            avg_s = kms * 1e-3 / launches
+            return {"avg_launch_ms": kms / launches, "launches": launches,
+                    "achieved": fl / avg_s / 1e12, "frac": fl / avg_s / 1e12 / peak_fl,
+                    "note": "lookahead off: the kernel alone on the GPU"}
+        finally:
+            hs.close()
+
     def profile(prec_name):
         pr = precs[prec_name]
         xx = x0.clone()
@@ -573,7 +612,9 @@ def main() -> int:
             else:
                 achieved, peak, unit, bound = fl / avg_s / 1e12, peak_fl, "TFLOP/s", "mfma"
             rf = {"bound": bound, "kernel": kern, "achieved": achieved, "peak": peak,
-                  "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(kern, sched),
+                  "unit": unit, "frac": achieved / peak,
+                  "isolated": isolated_bulk(kern, pr, sched, f32),
+                  "traffic": measured_traffic(kern, sched),
                   "mfma_counters": measured_mfma(kern, sched),
                   "schedule": {"step_panels": sched[0], "wide_rows": sched[1]},
                   "cholesky_frac_of_peak": result[prec_name].get("cholesky_frac_of_peak"),
