@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kRpyThreads) void rpy_assemble_batched_kernel(
 // <B, D_ij> = cI tr B + cRR R^T B R,
 //   g(B, R) = cI'(R) tr(B) R/|R| + cRR'(R) (R^T B R) R/|R| + cRR (B + B^T) R,
 // and the h* partial sum_j (cI tr Dbar_ij + cRR R^T Dbar_ij R) / h* (D - I
-// is linear in h*).  One work-item per bead i; j ascending.
+// is linear in h*).
 __device__ __forceinline__ void rpy_slopes(double R, double hstar, double a, double& cI,
                                            double& cRR, double& dcI, double& dcRR) {
   if (R >= 2.0 * a) {
@@ -96,17 +96,47 @@ __device__ __forceinline__ void rpy_slopes(double R, double hstar, double a, dou
   }
 }
 
-__global__ __launch_bounds__(kRpyThreads) void rpy_adjoint_kernel(
+// One workgroup per kAdjB beads i.  It walks the beads j in tiles of
+// kAdjB: the two 3 kAdjB x 3 kAdjB blocks of Dbar it needs, (rows of i,
+// columns of j) and (rows of j, columns of i), are staged in LDS by
+// consecutive threads reading consecutive rows of one column; then thread
+// (li, lj) evaluates the pair (i0 + li, j0 + lj).  Each thread keeps its
+// partial sums over its j's; at the end the kAdjB partials of bead i are
+// added in lj order.
+constexpr int kAdjB = 16;
+constexpr int kAdjS = 3 * kAdjB;  // block side in matrix rows
+
+__global__ __launch_bounds__(256) void rpy_adjoint_kernel(
     const double* __restrict__ x, const double* __restrict__ Db, int64_t ld, int N, double a,
     double* __restrict__ xbar, double* __restrict__ hpart, DevState* __restrict__ st) {
-  const int i = blockIdx.x * kRpyThreads + threadIdx.x;
-  if (i >= N) return;
+  static_assert(kAdjB * kAdjB == 256, "one pair per thread");
+  __shared__ double Sij[kAdjS][kAdjS + 1];  // [column (bead j)][row (bead i)]
+  __shared__ double Sji[kAdjS][kAdjS + 1];  // [column (bead i)][row (bead j)]
+  __shared__ double red[kAdjB][kAdjB][4];
+  const int t = threadIdx.x;
+  const int li = t % kAdjB, lj = t / kAdjB;
+  const int i0 = blockIdx.x * kAdjB;
+  const int i = i0 + li;
+  const int64_t r0i = 3 * (int64_t)i0;
+  const int nrow = 3 * N;
   double g0 = 0.0, g1 = 0.0, g2 = 0.0, hs = 0.0;
   bool coincident = false;
-  for (int j = 0; j < N; ++j) {
-    if (j == i) continue;
-    const double R[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1],
-                         x[3 * i + 2] - x[3 * j + 2]};
+  const double xi0 = (i < N) ? x[3 * i] : 0.0, xi1 = (i < N) ? x[3 * i + 1] : 0.0,
+               xi2 = (i < N) ? x[3 * i + 2] : 0.0;
+  for (int j0 = 0; j0 < N; j0 += kAdjB) {
+    const int64_t r0j = 3 * (int64_t)j0;
+    __syncthreads();  // the previous tile's blocks are no longer read
+    for (int e = t; e < kAdjS * kAdjS; e += 256) {
+      const int row = e % kAdjS, col = e / kAdjS;
+      const bool ok_ij = r0i + row < nrow && r0j + col < nrow;
+      const bool ok_ji = r0j + row < nrow && r0i + col < nrow;
+      Sij[col][row] = ok_ij ? Db[(r0j + col) * ld + r0i + row] : 0.0;
+      Sji[col][row] = ok_ji ? Db[(r0i + col) * ld + r0j + row] : 0.0;
+    }
+    __syncthreads();
+    const int j = j0 + lj;
+    if (i >= N || j >= N || j == i) continue;
+    const double R[3] = {xi0 - x[3 * j], xi1 - x[3 * j + 1], xi2 - x[3 * j + 2]};
     const double Rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
     if (Rn == 0.0) {
       coincident = true;
@@ -117,8 +147,8 @@ __global__ __launch_bounds__(kRpyThreads) void rpy_adjoint_kernel(
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        Bij[r][c] = Db[(3 * (int64_t)j + c) * ld + 3 * (int64_t)i + r];
-        B[r][c] = Bij[r][c] + Db[(3 * (int64_t)i + c) * ld + 3 * (int64_t)j + r];
+        Bij[r][c] = Sij[3 * lj + c][3 * li + r];
+        B[r][c] = Bij[r][c] + Sji[3 * li + c][3 * lj + r];
       }
     double cI, cRR, dcI, dcRR;  // per unit h*
     rpy_slopes(Rn, 1.0, a, cI, cRR, dcI, dcRR);
@@ -131,18 +161,32 @@ __global__ __launch_bounds__(kRpyThreads) void rpy_adjoint_kernel(
     }
     const double trB = B[0][0] + B[1][1] + B[2][2];
     const double q = R[0] * BR[0] + R[1] * BR[1] + R[2] * BR[2];
-    const double s = (dcI * trB + dcRR * q) / Rn;
-    g0 += s * R[0] + cRR * (BR[0] + BtR[0]);
-    g1 += s * R[1] + cRR * (BR[1] + BtR[1]);
-    g2 += s * R[2] + cRR * (BR[2] + BtR[2]);
+    const double sc = (dcI * trB + dcRR * q) / Rn;
+    g0 += sc * R[0] + cRR * (BR[0] + BtR[0]);
+    g1 += sc * R[1] + cRR * (BR[1] + BtR[1]);
+    g2 += sc * R[2] + cRR * (BR[2] + BtR[2]);
     hs += cI * (Bij[0][0] + Bij[1][1] + Bij[2][2]) +
           cRR * (R[0] * BijR[0] + R[1] * BijR[1] + R[2] * BijR[2]);
   }
-  xbar[3 * i] = g0;
-  xbar[3 * i + 1] = g1;
-  xbar[3 * i + 2] = g2;
-  hpart[i] = hs;
+  red[li][lj][0] = g0;
+  red[li][lj][1] = g1;
+  red[li][lj][2] = g2;
+  red[li][lj][3] = hs;
   if (coincident) st->status = BD_ERR_PARAM;
+  __syncthreads();
+  if (lj == 0 && i < N) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int k = 0; k < kAdjB; ++k) {
+      s0 += red[li][k][0];
+      s1 += red[li][k][1];
+      s2 += red[li][k][2];
+      s3 += red[li][k][3];
+    }
+    xbar[3 * i] = s0;
+    xbar[3 * i + 1] = s1;
+    xbar[3 * i + 2] = s2;
+    hpart[i] = s3;
+  }
 }
 
 // d phi / d h* = sum over beads of the partials, in bead order; the
@@ -175,8 +219,8 @@ hipError_t launch_rpy_adjoint(hipStream_t s, const bd_params_t& p, const double*
                               const double* Dbar, int64_t ld, double* xbar, double* hbar,
                               double* hpart, DevState* st) {
   const int N = p.n_beads;
-  BD_LAUNCH("rpy_adjoint", rpy_adjoint_kernel, dim3((N + kRpyThreads - 1) / kRpyThreads),
-            dim3(kRpyThreads), 0, s, x, Dbar, ld, N, p.a, xbar, hpart, st);
+  BD_LAUNCH("rpy_adjoint", rpy_adjoint_kernel, dim3((N + kAdjB - 1) / kAdjB), dim3(256), 0, s, x,
+            Dbar, ld, N, p.a, xbar, hpart, st);
   BD_LAUNCH("rpy_adjoint_finish", rpy_adjoint_finish_kernel, dim3(1), dim3(kRpyThreads), 0, s,
             hpart, N, p.hstar, xbar, hbar);
   return hipGetLastError();

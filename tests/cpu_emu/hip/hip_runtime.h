@@ -20,13 +20,24 @@ using std::min; using std::max;
 #define __forceinline__ inline
 #define __shared__ static
 #define __launch_bounds__(...)
+#define __align__(n) __attribute__((aligned(n)))
+// a device array's host address stands in for its device address
+#define HIP_SYMBOL(sym) (sym)
+template <typename T>
+inline int hipGetSymbolAddress(void** p, T& sym) {
+  *p = (void*)&sym;
+  return 0;
+}
+inline unsigned long long __umul64hi(unsigned long long a, unsigned long long b) {
+  return (unsigned long long)(((unsigned __int128)a * b) >> 64);
+}
 struct dim3 {
   unsigned x, y, z;
   constexpr dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
 };
 inline dim3 threadIdx, blockIdx, blockDim, gridDim;
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidDevice = 101 };
 typedef struct ihipStream_t* hipStream_t;
 typedef struct ihipEvent_t* hipEvent_t;
 inline hipError_t hipGetLastError() { return hipSuccess; }

@@ -126,3 +126,31 @@ def test_cholesky_adjoint_accesses_in_bounds(aemu, n, ld_pad):
     r = subprocess.run([aemu, str(n), str(ld_pad)], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, (n, ld_pad, r.stderr[-3000:])
     assert "status 0" in r.stdout
+
+
+# The adjoints of the assembly and of the noise product (differentiation):
+# ragged bead counts (one tile or less, tiles with a ragged last one) and
+# leading dimensions with padding.
+@pytest.fixture(scope="module")
+def raemu(tmp_path_factory):
+    return _build(tmp_path_factory, "rpy_adjoint_emu")
+
+
+@pytest.fixture(scope="module")
+def baemu(tmp_path_factory):
+    return _build(tmp_path_factory, "brownian_adjoint_emu")
+
+
+@pytest.mark.parametrize("N,pad", [(1, 0), (2, 3), (16, 0), (17, 5), (45, 1), (130, 0)])
+def test_rpy_adjoint_accesses_in_bounds(raemu, N, pad):
+    r = subprocess.run([raemu, str(N), str(pad)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, (N, pad, r.stderr[-3000:])
+    assert "status 0 (device 0)" in r.stdout
+
+
+@pytest.mark.parametrize("N,pad,padb", [(1, 0, 0), (2, 3, 0), (43, 0, 5), (86, 1, 2), (300, 0, 7)])
+def test_brownian_adjoint_accesses_in_bounds(baemu, N, pad, padb):
+    r = subprocess.run([baemu, str(N), str(pad), str(padb)], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, (N, pad, padb, r.stderr[-3000:])
+    assert "status 0" in r.stdout
