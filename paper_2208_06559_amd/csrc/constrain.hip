@@ -276,16 +276,18 @@ constexpr int kMvWaves = kMvThreads / 64;
 // CU; 1024: two workgroups per CU, for the ensembles' shorter chains).
 // kThreads: 1024, or 512 where each wave also does the work of the wave
 // eight places on (the two sets of phases kept in separate accumulators,
-// so every sum is formed in the same order as with 1024 threads).  LDS:
-// sx, sf (3 kChunk each) and red (kMvWaves x 3 x kMvI), from the caller.
+// so every sum is formed in the same order as with 1024 threads).  LDS,
+// from the caller: sxf (6 kChunk doubles, 16-byte aligned: bead j's
+// position and force side by side, x0 x1 x2 f0 f1 f2, read as three
+// 16-byte words) and red (kMvWaves x 3 x kMvI).
 constexpr int kMvLds = 3 * kMvWaves * kMvI;
 
 template <int kChunk, int kThreads>
 __device__ __forceinline__ void dmatvec_body(int bx, const double* __restrict__ x,
                                              const double* __restrict__ f, double* __restrict__ r,
                                              int N, const RpyConst& kc,
-                                             const DevState* __restrict__ st, double* sx,
-                                             double* sf, double* redp) {
+                                             const DevState* __restrict__ st, double* sxf,
+                                             double* redp) {
   static_assert(kThreads == 1024 || kThreads == 512, "one or two phase sets per wave");
   constexpr int kV = kMvThreads / kThreads;  // phase sets per wave
   constexpr int kW = kThreads / 64;          // waves
@@ -303,8 +305,9 @@ __device__ __forceinline__ void dmatvec_body(int bx, const double* __restrict__ 
     const int nj = (N - j0 < kChunk) ? N - j0 : kChunk;
     __syncthreads();
     for (int e = tid; e < 3 * nj; e += kThreads) {
-      sx[e] = x[3 * j0 + e];
-      sf[e] = f[3 * j0 + e];
+      const int jb = e / 3, c = e - 3 * jb;
+      sxf[6 * jb + c] = x[3 * j0 + e];
+      sxf[6 * jb + 3 + c] = f[3 * j0 + e];
     }
     __syncthreads();
     for (int jt = 4 * w + jp; jt < nj; jt += 8 * kMvWaves) {
@@ -314,11 +317,15 @@ __device__ __forceinline__ void dmatvec_body(int bx, const double* __restrict__ 
         if (jj >= nj) break;
         const int jb = jj + 4 * kMvWaves;
         const bool hb = jb < nj;
-        const int qa = 3 * jj, qb = 3 * (hb ? jb : jj);
-        const double fa0 = sf[qa], fa1 = sf[qa + 1], fa2 = sf[qa + 2];
-        const double fb0 = sf[qb], fb1 = sf[qb + 1], fb2 = sf[qb + 2];
-        const double Ra0 = xi0 - sx[qa], Ra1 = xi1 - sx[qa + 1], Ra2 = xi2 - sx[qa + 2];
-        const double Rb0 = xi0 - sx[qb], Rb1 = xi1 - sx[qb + 1], Rb2 = xi2 - sx[qb + 2];
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2* pa = reinterpret_cast<const d2*>(sxf + 6 * jj);
+        const d2* pb = reinterpret_cast<const d2*>(sxf + 6 * (hb ? jb : jj));
+        const d2 ua0 = pa[0], ua1 = pa[1], ua2 = pa[2];  // x0 x1 | x2 f0 | f1 f2
+        const d2 ub0 = pb[0], ub1 = pb[1], ub2 = pb[2];
+        const double fa0 = ua1[1], fa1 = ua2[0], fa2 = ua2[1];
+        const double fb0 = ub1[1], fb1 = ub2[0], fb2 = ub2[1];
+        const double Ra0 = xi0 - ua0[0], Ra1 = xi1 - ua0[1], Ra2 = xi2 - ua1[0];
+        const double Rb0 = xi0 - ub0[0], Rb1 = xi1 - ub0[1], Rb2 = xi2 - ub1[0];
         const double R2a = Ra0 * Ra0 + Ra1 * Ra1 + Ra2 * Ra2;
         const double R2b = Rb0 * Rb0 + Rb1 * Rb1 + Rb2 * Rb2;
         double cIa, cRRa, ya, cIb, cRRb, yb;
@@ -382,8 +389,9 @@ __global__ __launch_bounds__(kMvThreads / 2) void dmatvec_kernel(const double* _
                                                        const double* __restrict__ f,
                                                        double* __restrict__ r, int N, RpyConst kc,
                                                        const DevState* __restrict__ st) {
-  __shared__ double sx[3 * 2048], sf[3 * 2048], red[kMvLds];
-  dmatvec_body<2048, kMvThreads / 2>(blockIdx.x, x, f, r, N, kc, st, sx, sf, red);
+  __shared__ __attribute__((aligned(16))) double sxf[6 * 2048];
+  __shared__ double red[kMvLds];
+  dmatvec_body<2048, kMvThreads / 2>(blockIdx.x, x, f, r, N, kc, st, sxf, red);
 }
 
 // ------------------------------------------------------------ controller
@@ -1008,7 +1016,7 @@ __device__ __noinline__ void ps_matvec(int wg, int nwg, const double* __restrict
   const int nblk = (N + kMvI - 1) / kMvI;
   for (int blk = wg; blk < nblk; blk += nwg)
     dmatvec_body<2048, kCtlThreads>(blk, x_old, b.f, b.r, N, kc, nullptr, arena,
-                                    arena + 3 * 2048, arena + 6 * 2048);
+                                    arena + 6 * 2048);
 }
 
 template <int kRr>
@@ -1024,7 +1032,7 @@ __global__ __launch_bounds__(kCtlThreads) void constrain_persistent_kernel(
     const double* __restrict__ x_old, Bufs b, double* __restrict__ xs,
     double* __restrict__ T_out, int N, double dt, double bl, double tol, int maxit, RpyConst kc,
     DevState* __restrict__ st, int cap) {
-  __shared__ double arena[kPsLds];
+  __shared__ __attribute__((aligned(16))) double arena[kPsLds];
   __shared__ int flag;
   const uint32_t nwg = gridDim.x;
   const int wg = blockIdx.x;
@@ -1118,9 +1126,10 @@ __global__ __launch_bounds__(kMvThreads / 2) void dmatvec_batched_kernel(
   const int ci = find_chain(prefix, count, t);
   const ChainDesc& c = cd[ci];
   const Bufs b = carve(c.cons, c.N);
-  __shared__ double sx[3 * 1024], sf[3 * 1024], red[kMvLds];
+  __shared__ __attribute__((aligned(16))) double sxf[6 * 1024];
+  __shared__ double red[kMvLds];
   dmatvec_body<1024, kMvThreads / 2>(t - prefix[ci], c.x, b.f, b.r, c.N, rpy_const(c.hstar, c.a),
-                                     c.st, sx, sf, red);
+                                     c.st, sxf, red);
 }
 
 __global__ __launch_bounds__(kCtlThreads) void newton_controller_batched_kernel(
