@@ -993,7 +993,11 @@ template <typename T, int TS, bool AL>
 __device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, int64_t ld,
                                                  const T* __restrict__ L, int64_t ldl, int64_t m,
                                                  int kdim, int tiles, int nnext) {
-  constexpr int KC = SyrkCfg<T>::KC;
+  // The FP32 next-column update (TS = 64) takes half-width chunks and 64
+  // registers, so that its workgroups fit on a CU beside two bulk ones
+  // (448 of 512 registers per SIMD, 128 of 160 KB of LDS) instead of
+  // waiting for one of them to finish; same sums in the same order.
+  constexpr int KC = (sizeof(T) == 4 && TS == 64) ? 16 : SyrkCfg<T>::KC;
   typedef typename SyrkCfg<T>::acc_t acc_t;
   constexpr int WT = TS / 2;    // each wave owns a WT x WT quadrant
   constexpr int NBK = WT / 16;  // 16 x 16 MFMA blocks per quadrant side
@@ -1140,6 +1144,18 @@ __device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, 
     __syncthreads();
   }
   if (!active) return;
+  if constexpr (sizeof(T) == 4 && TS == 64) {  // 64 registers: one batch at a time
+    chunk((nch - 1) & 1)(acc);
+    if (whole) {
+#pragma unroll
+      for (int bt = 0; bt < NBT; ++bt) {
+        batch_t cv;
+        cload(bt * EB, cv);
+        cstore(bt * EB, cv);
+      }
+      return;
+    }
+  } else {
   batch_t c0;
   {
     auto run = chunk((nch - 1) & 1);
@@ -1158,6 +1174,7 @@ __device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, 
       }
     }
     return;
+  }
   }
   // other quadrants: element by element, masked
 #pragma unroll
@@ -1184,11 +1201,12 @@ __device__ __forceinline__ void syrk_update_body(int t, double* __restrict__ C, 
 
 // XCD x receives workgroups x, x+8, ...: cnt(x) = base + (x < rem) of them;
 // the q-th of them takes tile x*base + min(x, rem) + q (a bijection).
+template <typename T, int TS>
+constexpr int syrk_min_blocks() { return (sizeof(T) == 4 && TS == 64) ? 8 : 2; }
 template <typename T, int TS, bool AL>
-__global__ __launch_bounds__(256, 2) void syrk_update_kernel(double* __restrict__ C, int64_t ld,
-                                                              const T* __restrict__ L, int64_t ldl,
-                                                              int64_t m, int kdim, int tiles,
-                                                              int nnext) {
+__global__ __launch_bounds__(256, (syrk_min_blocks<T, TS>())) void syrk_update_kernel(
+    double* __restrict__ C, int64_t ld, const T* __restrict__ L, int64_t ldl, int64_t m, int kdim,
+    int tiles, int nnext) {
   syrk_update_body<T, TS, AL>(xcd_contiguous(blockIdx.x, gridDim.x), C, ld, L, ldl, m, kdim, tiles,
                           nnext);
 }
@@ -1245,7 +1263,7 @@ __host__ __device__ inline int64_t syrk_tile_count(int64_t m, int ts, int tiles,
 // One flattened grid over every chain's tiles, each XCD taking a contiguous
 // range of (chain, tile).
 template <typename T, int TS, bool AL>
-__global__ __launch_bounds__(256, 2) void syrk_update_batched_kernel(
+__global__ __launch_bounds__(256, (syrk_min_blocks<T, TS>())) void syrk_update_batched_kernel(
     const ChainDesc* __restrict__ cd, const int32_t* __restrict__ prefix, int z, int64_t k0,
     int64_t r0, int kdim, int tiles, int nnext_panels, int pidx) {
   const int tg = xcd_contiguous(blockIdx.x, gridDim.x);
