@@ -85,6 +85,11 @@ struct StepLayout {
   size_t d, chol, brown, cons, y, xs, total;
 };
 
+// The partial sums follow xi in the noise region.
+double* step_ypart(char* base, const StepLayout& L, int64_t n) {
+  return reinterpret_cast<double*>(base + L.brown + bd::align_up(sizeof(double) * (size_t)n, 256));
+}
+
 // batched: the layout of one chain of an ensemble
 StepLayout step_layout(int64_t n, bd_precision_t prec, bool batched = false) {
   StepLayout L;
@@ -95,8 +100,9 @@ StepLayout step_layout(int64_t n, bd_precision_t prec, bool batched = false) {
   off += bd::align_up(batched ? bd::cholesky_batched_workspace_bytes(n, prec)
                               : bd::cholesky_workspace_bytes(n, prec),
                       256);
+  // the noise xi, then the factorisation's partial sums of c_B L xi
   L.brown = off;
-  off += bd::align_up(bd::brownian_workspace_bytes(n), 256);
+  off += bd::align_up(sizeof(double) * (size_t)n, 256) + bd::noise_part_bytes(n);
   L.cons = off;
   off += bd::align_up(bd::constrain_workspace_bytes(n / 3), 256);
   L.y = off;
@@ -200,11 +206,13 @@ bd_status_t enter(bd_handle_t h) {
 }
 
 hipError_t launch_cholesky_tuned(bd_handle_t h, hipStream_t s, int64_t n, double* A, int64_t ld,
-                                 bd_precision_t prec, void* ws) {
+                                 bd_precision_t prec, void* ws, const double* xi = nullptr,
+                                 double* y = nullptr, double cB = 0.0, double* ypart = nullptr) {
   int sp;
   int64_t wr;
   schedule_for(h, n, prec, sp, wr);
-  return bd::launch_cholesky(s, h->aux, h->ev, n, A, ld, prec, ws, h->st, sp, wr, h->tile_potrf);
+  return bd::launch_cholesky(s, h->aux, h->ev, n, A, ld, prec, ws, h->st, sp, wr, h->tile_potrf,
+                             xi, y, cB, ypart);
 }
 
 hipError_t reset(bd_handle_t h) {
@@ -227,9 +235,8 @@ struct bd_ensemble_s {
   int pairs_hint;
   int step_panels;                   // Cholesky panels per step (2 or 4)
   int32_t* mv_prefix;                // device: flattened grids (matrix-free product,
-  int32_t* rpy_prefix;               // assembly, noise product tiles)
-  int32_t* trmv_prefix;
-  int mv_blocks, rpy_blocks, trmv_blocks;
+  int32_t* rpy_prefix;               // assembly)
+  int mv_blocks, rpy_blocks;
   bd::BatchTables tb;                // flattened grids of the factorisation
   int32_t* tb_dev;                   // device copy of tb.host
   // a captured step (bd_ensemble_capture): its executable graph, the stream
@@ -489,11 +496,13 @@ bd_status_t bd_step(bd_handle_t h, const bd_params_t* p, int64_t step, double* d
   const int64_t ld = step_ld(n);
   hipStream_t s = h->stream;
   hipError_t he = reset(h);
+  // the noise first: the factorisation call ends with y = c_B L xi
+  double* xi = reinterpret_cast<double*>(base + L.brown);
   if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
+  if (he == hipSuccess) he = bd::launch_noise(s, *p, step, xi);
   if (he == hipSuccess)
-    he = launch_cholesky_tuned(h, s, n, D, ld, prec, base + L.chol);
-  if (he == hipSuccess)
-    he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
+    he = launch_cholesky_tuned(h, s, n, D, ld, prec, base + L.chol, xi, y, bd::noise_coeff(*p),
+                               step_ypart(base, L, n));
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);
   if (he == hipSuccess)
     he = bd::launch_constrain(s, *p, d_x, xs, nullptr, base + L.cons, h->st, h->host,
@@ -547,9 +556,10 @@ bd_status_t bd_step_adjoint(bd_handle_t h, const bd_params_t* p, int64_t step, c
   // tensions T and x^{t+dt} (in xs)
   hipError_t he = reset(h);
   if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
+  if (he == hipSuccess) he = bd::launch_noise(s, *p, step, xi);
   if (he == hipSuccess)
-    he = launch_cholesky_tuned(h, s, n, D, ld, BD_PREC_FP64, fwd + L.chol);
-  if (he == hipSuccess) he = bd::launch_brownian(s, *p, step, D, ld, y, xi, fwd + L.brown);
+    he = launch_cholesky_tuned(h, s, n, D, ld, BD_PREC_FP64, fwd + L.chol, xi, y,
+                               bd::noise_coeff(*p), step_ypart(fwd, L, n));
   if (he == hipSuccess) he = bd::launch_predictor(s, *p, d_x, y, xs);
   if (he == hipSuccess)
     he = bd::launch_constrain(s, *p, d_x, xs, T, fwd + L.cons, h->st, h->host, &h->pairs_hint,
@@ -596,11 +606,12 @@ bd_status_t bd_step_fraenkel(bd_handle_t h, const bd_params_t* p, double k_sprin
   const int64_t ld = step_ld(n);
   hipStream_t s = h->stream;
   hipError_t he = reset(h);
+  double* xi = reinterpret_cast<double*>(base + L.brown);
   if (he == hipSuccess) he = bd::launch_rpy_assemble(s, *p, d_x, D, ld, BD_FILL_LOWER);
+  if (he == hipSuccess) he = bd::launch_noise(s, *p, step, xi);
   if (he == hipSuccess)
-    he = launch_cholesky_tuned(h, s, n, D, ld, prec, base + L.chol);
-  if (he == hipSuccess)
-    he = bd::launch_brownian(s, *p, step, D, ld, y, nullptr, base + L.brown);
+    he = launch_cholesky_tuned(h, s, n, D, ld, prec, base + L.chol, xi, y, bd::noise_coeff(*p),
+                               step_ypart(base, L, n));
   if (he == hipSuccess) he = bd::launch_spring_forces(s, d_x, p->n_beads, k_spring, p->b, f);
   if (he == hipSuccess) he = bd::launch_dmatvec(s, *p, d_x, f, v, h->st);
   if (he == hipSuccess) he = bd::launch_fraenkel_update(s, *p, k_spring, d_x, v, y, h->st);
@@ -722,7 +733,6 @@ static void ensemble_release(bd_ensemble_s* e) {
   if (e->cd) (void)hipFree(e->cd);
   if (e->mv_prefix) (void)hipFree(e->mv_prefix);
   if (e->rpy_prefix) (void)hipFree(e->rpy_prefix);
-  if (e->trmv_prefix) (void)hipFree(e->trmv_prefix);
   if (e->tb_dev) (void)hipFree(e->tb_dev);
   if (e->st) (void)hipFree(e->st);
   if (e->host_st) (void)hipHostFree(e->host_st);
@@ -762,8 +772,8 @@ static bd_status_t ensemble_create_impl(bd_handle_t h, int32_t n_chains, const b
   e->st = nullptr;
   e->host_st = nullptr;
   e->pairs_hint = 0;
-  e->mv_prefix = e->rpy_prefix = e->trmv_prefix = nullptr;
-  e->mv_blocks = e->rpy_blocks = e->trmv_blocks = 0;
+  e->mv_prefix = e->rpy_prefix = nullptr;
+  e->mv_blocks = e->rpy_blocks = 0;
   e->tb_dev = nullptr;
   e->gexec = nullptr;
   e->cap = nullptr;
@@ -782,8 +792,7 @@ static bd_status_t ensemble_create_impl(bd_handle_t h, int32_t n_chains, const b
       hipHostMalloc(&e->host_st, sizeof(DevState) * (size_t)n_chains, hipHostMallocDefault) !=
           hipSuccess ||
       hipMalloc(&e->mv_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess ||
-      hipMalloc(&e->rpy_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess ||
-      hipMalloc(&e->trmv_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess) {
+      hipMalloc(&e->rpy_prefix, sizeof(int32_t) * ((size_t)n_chains + 1)) != hipSuccess) {
     return BD_ERR_ALLOC;
   }
   e->host.resize((size_t)n_chains);
@@ -819,7 +828,7 @@ static bd_status_t ensemble_create_impl(bd_handle_t h, int32_t n_chains, const b
       d.P32[1] = reinterpret_cast<float*>(pc + bd::p32_copy_bytes(n));
     }
     d.xi = reinterpret_cast<double*>(base + L.brown);
-    d.part = reinterpret_cast<double*>(base + L.brown + bd::align_up(sizeof(double) * n, 256));
+    d.ypart = step_ypart(base, L, n);
     d.y = reinterpret_cast<double*>(base + L.y);
     d.xs = reinterpret_cast<double*>(base + L.xs);
     d.cons = base + L.cons;
@@ -834,23 +843,20 @@ static bd_status_t ensemble_create_impl(bd_handle_t h, int32_t n_chains, const b
   std::stable_sort(e->host.begin(), e->host.end(),
                    [](const bd::ChainDesc& a, const bd::ChainDesc& b) { return a.n > b.n; });
   memset(e->host_st, 0, sizeof(DevState) * (size_t)n_chains);
-  std::vector<int32_t> prefix((size_t)n_chains + 1, 0), rpre(prefix), tpre(prefix);
-  int64_t pm = 0, pr = 0, pt = 0;  // grids must stay within int32
+  std::vector<int32_t> prefix((size_t)n_chains + 1, 0), rpre(prefix);
+  int64_t pm = 0, pr = 0;  // grids must stay within int32
   for (int32_t c = 0; c < n_chains; ++c) {
     const bd::ChainDesc& d = e->host[(size_t)c];
     pm += bd::constrain_mv_blocks(d.N);
     pr += bd::rpy_batched_blocks(d.N);
-    pt += bd::trmv_batched_blocks(d.n);
-    if (pm > INT32_MAX || pr > INT32_MAX || pt > INT32_MAX) {
+    if (pm > INT32_MAX || pr > INT32_MAX) {
         return BD_ERR_UNSUPPORTED;
     }
     prefix[(size_t)c + 1] = (int32_t)pm;
     rpre[(size_t)c + 1] = (int32_t)pr;
-    tpre[(size_t)c + 1] = (int32_t)pt;
   }
   e->mv_blocks = prefix[(size_t)n_chains];
   e->rpy_blocks = rpre[(size_t)n_chains];
-  e->trmv_blocks = tpre[(size_t)n_chains];
   // record the factorisation's flattened grids (no launches), then upload
   e->tb.record = true;
   const hipError_t rec = bd::launch_cholesky_batched(h->stream, h->aux, h->ev, e->cd,
@@ -867,8 +873,6 @@ static bd_status_t ensemble_create_impl(bd_handle_t h, int32_t n_chains, const b
       hipMemcpy(e->mv_prefix, prefix.data(), sizeof(int32_t) * prefix.size(),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(e->rpy_prefix, rpre.data(), sizeof(int32_t) * rpre.size(),
-                hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(e->trmv_prefix, tpre.data(), sizeof(int32_t) * tpre.size(),
                 hipMemcpyHostToDevice) != hipSuccess ||
       (!e->tb.host.empty() &&
        hipMemcpy(e->tb_dev, e->tb.host.data(), sizeof(int32_t) * e->tb.host.size(),
@@ -906,12 +910,10 @@ static hipError_t ensemble_step_launches(bd_ensemble_s* e, hipStream_t s, int64_
   hipError_t he = hipGetLastError();
   if (he == hipSuccess)
     he = bd::launch_rpy_assemble_batched(s, e->cd, z, e->rpy_prefix, e->rpy_blocks);
+  if (he == hipSuccess) he = bd::launch_noise_batched(s, e->cd, z, max_n, step, d_step);
   if (he == hipSuccess)
     he = bd::launch_cholesky_batched(s, h->aux, h->ev, e->cd, e->host.data(), z, e->prec,
-                                     e->step_panels, &e->tb);
-  if (he == hipSuccess)
-    he = bd::launch_brownian_batched(s, e->cd, z, max_n, step, e->trmv_prefix, e->trmv_blocks,
-                                     d_step);
+                                     e->step_panels, &e->tb, true);
   if (he == hipSuccess) he = bd::launch_predictor_batched(s, e->cd, z, e->max_beads);
   if (he == hipSuccess)
     he = bd::launch_constrain_batched(s, e->cd, z, e->max_beads, e->mv_prefix, e->mv_blocks,

@@ -136,20 +136,6 @@ __global__ __launch_bounds__(256) void noise_batched_kernel(const ChainDesc* __r
   noise_body(blockIdx.x, c.xi, c.n, c.seed, c.chain_id, st, c.uniform);
 }
 
-// one flattened grid: chain c owns trmv_batched_blocks(n_c) tiles
-__global__ __launch_bounds__(kTv) void trmv_tile_batched_kernel(const ChainDesc* __restrict__ cd,
-                                                                 const int32_t* __restrict__ prefix,
-                                                                 int count) {
-  const int ci = find_chain(prefix, count, blockIdx.x);
-  const ChainDesc& c = cd[ci];
-  trmv_tile_body(blockIdx.x - prefix[ci], c.D, c.ld, c.n, c.xi, c.part);
-}
-
-__global__ __launch_bounds__(256) void trmv_reduce_batched_kernel(const ChainDesc* __restrict__ cd) {
-  const ChainDesc& c = cd[blockIdx.z];
-  trmv_reduce_body(blockIdx.x, c.part, c.n, c.cB, c.y);
-}
-
 __global__ __launch_bounds__(256) void predictor_batched_kernel(const ChainDesc* __restrict__ cd) {
   const ChainDesc& c = cd[blockIdx.z];
   const double* k = c.kappa;
@@ -301,21 +287,23 @@ hipError_t launch_predictor(hipStream_t s, const bd_params_t& p, const double* x
   return hipGetLastError();
 }
 
-int trmv_batched_blocks(int64_t n) {
-  const int64_t nt = trmv_tiles(n);
-  return (int)(nt * (nt + 1) / 2);
+double noise_coeff(const bd_params_t& p) {
+  return (p.noise == BD_NOISE_UNIFORM_PAPER) ? sqrt(6.0 * p.dt) : sqrt(2.0 * p.dt);
 }
 
-hipError_t launch_brownian_batched(hipStream_t s, const ChainDesc* cd, int count, int64_t max_n,
-                                   int64_t step, const int32_t* tile_prefix, int tile_blocks,
-                                   const int64_t* d_step) {
+hipError_t launch_noise(hipStream_t s, const bd_params_t& p, int64_t step, double* xi) {
+  const int64_t n = 3 * (int64_t)p.n_beads;
+  const int64_t nblk = (n + 3) / 4;
+  BD_LAUNCH("noise", noise_kernel, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, s, xi, n,
+            p.seed, p.chain_id, (uint64_t)step, p.noise == BD_NOISE_UNIFORM_PAPER);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise_batched(hipStream_t s, const ChainDesc* cd, int count, int64_t max_n,
+                                int64_t step, const int64_t* d_step) {
   const int64_t nblk = (max_n + 3) / 4;
   BD_LAUNCH("noise_batched", noise_batched_kernel,
             dim3((unsigned)((nblk + 255) / 256), 1, count), dim3(256), 0, s, cd, (uint64_t)step, d_step);
-  BD_LAUNCH("trmv_tile_batched", trmv_tile_batched_kernel, dim3((unsigned)tile_blocks),
-            dim3(kTv), 0, s, cd, tile_prefix, count);
-  BD_LAUNCH("trmv_reduce_batched", trmv_reduce_batched_kernel,
-            dim3((unsigned)((max_n + 255) / 256), 1, count), dim3(256), 0, s, cd);
   return hipGetLastError();
 }
 

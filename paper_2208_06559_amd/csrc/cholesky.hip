@@ -848,6 +848,17 @@ __global__ __launch_bounds__(256) void potrf_tile_kernel(double* __restrict__ A,
   potrf_tile_body(A, ld, k, nb, W, st);
 }
 
+// W bytes of each lane from global memory straight into LDS, at the
+// wave-uniform address `lds` plus W times the lane index.
+template <int W>
+__device__ __forceinline__ void load_to_lds(const void* g, void* lds) {
+  static_assert(W == 16 || W == 4, "load width");
+  if constexpr (W == 16)
+    __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds(g, lds, 4, 0, 0);
+}
+
 // ------------------------------------------------------------------------
 // 2. Panel solve X L11^T = A21 for a block of 32 rows, by blocked forward
 //    substitution over the four 32-column sub-panels:
@@ -898,10 +909,19 @@ __device__ __forceinline__ void solve_subpanel(double (&x)[NB / 4], const double
     for (int q = 0; q < 4; ++q) x[c0 / 4 + 4 * jt + q] = y[jt][q];
 }
 
+// With xi non-null (the ensemble's fused noise product) the row block's
+// share of the noise product is stored as well: yp(k + nb + row) =
+// cB sum_c X(row, c) xi(k + c), yp this panel's row of partial sums (the
+// rows below the diagonal block; store only, so no read latency lands on
+// the chain of panels).  Each lane sums the columns c = lk (mod 4) in
+// order and the four sums are combined pairwise, (s0 + s1) + (s2 + s3);
+// noise_part_kernel forms the same sums in the same order.
 __device__ __forceinline__ void panel_solve_body(int bx, double* __restrict__ A, int64_t ld,
                                                  int64_t k, int nb, int64_t m,
                                                  const double* __restrict__ W,
-                                                 float* __restrict__ P32, int64_t ldp) {
+                                                 float* __restrict__ P32, int64_t ldp,
+                                                 const double* __restrict__ xi,
+                                                 double* __restrict__ yp, double cB) {
   static_assert(NSB == 4 && res_row_f64_is_lk_plus_4r, "register layout of the panel solve");
   __builtin_amdgcn_s_setprio(3);  // critical path, like the diagonal block
   const int tid = threadIdx.x;
@@ -916,10 +936,31 @@ __device__ __forceinline__ void panel_solve_body(int bx, double* __restrict__ A,
     const int c = 4 * t + lk;
     x[t] = (live && c < nb) ? A21[(int64_t)c * ld + row] : 0.0;
   }
+  // xi(k .. k + NB - 1) for the noise share, one copy per wave, straight to
+  // LDS (no registers), issued after the row block's loads so that waiting
+  // for those does not wait for it: it lands while the rows are solved
+  __shared__ __attribute__((aligned(16))) double sxi[kPsThreads / 64][NB];
+  if (xi) {
+#pragma unroll
+    for (int u = 0; u < NB * 8 / 256; ++u)
+      load_to_lds<4>(reinterpret_cast<const char*>(xi + k) + 256 * u + 4 * lane, &sxi[w][32 * u]);
+  }
   solve_subpanel<0>(x, L11, ld, W, lr, lk);
   solve_subpanel<1>(x, L11, ld, W + SBB, lr, lk);
   solve_subpanel<2>(x, L11, ld, W + 2 * SBB, lr, lk);
   solve_subpanel<3>(x, L11, ld, W + 3 * SBB, lr, lk);
+  if (xi) {  // lanes lr + 16 lk hold the columns lk (mod 4) of one row
+    const double* sxi_w = sxi[w];
+    double sxs = 0.0;
+#pragma unroll
+    for (int t = 0; t < NB / 4; ++t) {
+      const int c = 4 * t + lk;
+      if (c < nb) sxs += x[t] * sxi_w[c];
+    }
+    sxs += __shfl_xor(sxs, 16, 64);
+    sxs += __shfl_xor(sxs, 32, 64);
+    if (live && lk == 0) yp[k + nb + row] = cB * sxs;
+  }
   if (!live) return;
 #pragma unroll
   for (int t = 0; t < NB / 4; ++t) {
@@ -934,7 +975,89 @@ __device__ __forceinline__ void panel_solve_body(int bx, double* __restrict__ A,
 __global__ __launch_bounds__(kPsThreads) void panel_solve_kernel(
     double* __restrict__ A, int64_t ld, int64_t k, int nb, int64_t m, const double* __restrict__ W,
     float* __restrict__ P32, int64_t ldp) {
-  panel_solve_body(blockIdx.x, A, ld, k, nb, m, W, P32, ldp);
+  panel_solve_body(blockIdx.x, A, ld, k, nb, m, W, P32, ldp, nullptr, nullptr, 0.0);
+}
+
+// The panels' shares of the noise product y = cB L xi for panels already
+// factored (one chain: launched beside the factorisation, after each
+// step's trailing update, instead of adding work to each panel solve on
+// the chain of diagonal blocks and panel solves).  Block (bx, j) stores,
+// for the rows i = i0 + 256 bx + t below panel p = p0 + j,
+// ypart(p, i) = cB sum_c L(i, p NB + c) xi(p NB + c), summed exactly as the
+// fused panel solve sums it: four running sums over c = q (mod 4) and
+// (s0 + s1) + (s2 + s3), so that one chain and an ensemble chain agree to
+// the bit.  Lanes read consecutive rows of one column (512 bytes a wave).
+constexpr int kNpRows = 256;
+
+__global__ __launch_bounds__(kNpRows) void noise_part_kernel(const double* __restrict__ A,
+                                                            int64_t ld, int64_t n, int64_t p0,
+                                                            int64_t i0,
+                                                            const double* __restrict__ xi,
+                                                            double* __restrict__ ypart,
+                                                            double cB) {
+  const int64_t pn = p0 + blockIdx.y;
+  const int64_t k = pn * NB;
+  const int64_t i = i0 + (int64_t)blockIdx.x * kNpRows + threadIdx.x;
+  if (i < k + NB || i >= n) return;
+  const double* Li = A + k * ld + i;
+  const double* xk = xi + k;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 8
+  for (int t = 0; t < NB / 4; ++t) {
+    const int64_t c = 4 * t;
+    s0 += Li[c * ld] * xk[c];
+    s1 += Li[(c + 1) * ld] * xk[c + 1];
+    s2 += Li[(c + 2) * ld] * xk[c + 2];
+    s3 += Li[(c + 3) * ld] * xk[c + 3];
+  }
+  ypart[pn * n + i] = cB * ((s0 + s1) + (s2 + s3));
+}
+
+// The noise product's sums, after the factorisation: row i of block b gets
+// y(i) = sum_{p < b} ypart(p, i) (the panels' shares, in panel order) +
+// cB sum_{c <= r} L(i, bNB + c) xi(bNB + c) (its diagonal block, r = i - bNB).
+// One thread per row; lanes read consecutive rows of one column.
+__device__ __forceinline__ void noise_sum_body(int blk, const double* __restrict__ A, int64_t ld,
+                                               int64_t n, const double* __restrict__ xi,
+                                               const double* __restrict__ ypart,
+                                               double* __restrict__ y, double cB) {
+  const int64_t k = (int64_t)blk * NB;
+  const int r = threadIdx.x;
+  if (k + r >= n) return;
+  // sixteen loads in flight at a time, the sums still in order
+  constexpr int U = 16;
+  double s = 0.0;
+  int p = 0;
+  for (; p + U <= blk; p += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = ypart[(int64_t)(p + u) * n + k + r];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
+  for (; p < blk; ++p) s += ypart[(int64_t)p * n + k + r];
+  const double* Akk = A + k * ld + k;
+  double sxi = 0.0;
+  int c = 0;
+  for (; c + U <= r + 1; c += U) {
+    double a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] = Akk[(int64_t)(c + u) * ld + r];
+      b[u] = xi[k + c + u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) sxi += a[u] * b[u];
+  }
+  for (; c <= r; ++c) sxi += Akk[(int64_t)c * ld + r] * xi[k + c];
+  y[k + r] = s + cB * sxi;
+}
+
+__global__ __launch_bounds__(NB) void noise_sum_kernel(const double* __restrict__ A, int64_t ld,
+                                                       int64_t n, const double* __restrict__ xi,
+                                                       const double* __restrict__ ypart,
+                                                       double* __restrict__ y, double cB) {
+  noise_sum_body(blockIdx.x, A, ld, n, xi, ypart, y, cB);
 }
 
 // ------------------------------------------------------------------------
@@ -971,17 +1094,6 @@ struct SyrkCfg<float> {
 // tile columns (the next step's panels, updated ahead), or every lower tile
 // outside those columns.
 enum { kTilesAll = 0, kTilesNext = 1, kTilesRest = 2 };
-
-// W bytes of each lane from global memory straight into LDS, at the
-// wave-uniform address `lds` plus W times the lane index.
-template <int W>
-__device__ __forceinline__ void load_to_lds(const void* g, void* lds) {
-  static_assert(W == 16 || W == 4, "load width");
-  if constexpr (W == 16)
-    __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0);
-  else
-    __builtin_amdgcn_global_load_lds(g, lds, 4, 0, 0);
-}
 
 // AL: the operand L and the matrix C start on 16-byte boundaries and their
 // column strides are multiples of 16 bytes.  Then each lane moves 16 bytes
@@ -1229,13 +1341,21 @@ __global__ __launch_bounds__(256) void potrf_tile_batched_kernel(const ChainDesc
 // one flattened grid over every chain's row blocks.
 __global__ __launch_bounds__(kPsThreads) void panel_solve_batched_kernel(
     const ChainDesc* __restrict__ cd, const int32_t* __restrict__ prefix, int z, int64_t k0,
-    int64_t kp, int pidx) {
+    int64_t kp, int pidx, int noise) {
   const int ci = find_chain(prefix, z, blockIdx.x);
   const ChainDesc& c = cd[ci];
   const int64_t m = c.n - kp - NB;
   float* P = c.P32[pidx];
   if (P) P += (kp - k0) * p32_ld(c.n) + kp + NB;
-  panel_solve_body(blockIdx.x - prefix[ci], c.D, c.ld, kp, NB, m, c.W, P, p32_ld(c.n));
+  panel_solve_body(blockIdx.x - prefix[ci], c.D, c.ld, kp, NB, m, c.W, P, p32_ld(c.n),
+                   noise ? c.xi : nullptr, c.ypart + (kp / NB) * c.n, c.cB);
+}
+
+// Chain blockIdx.z's rows.
+__global__ __launch_bounds__(NB) void noise_sum_batched_kernel(const ChainDesc* __restrict__ cd) {
+  const ChainDesc& c = cd[blockIdx.z];
+  if ((int64_t)blockIdx.x * NB >= c.n) return;
+  noise_sum_body(blockIdx.x, c.D, c.ld, c.n, c.xi, c.ypart, c.y, c.cB);
 }
 
 // Tiles of tile set `tiles` in an m x m trailing matrix with TS x TS tiles;
@@ -1312,6 +1432,12 @@ struct CholCtx {
   int64_t wide_rows;  // four-panel steps only while more rows than this remain
   bool tile_potrf;    // diagonal blocks on matrix cores (else register tiles)
   DevState* st;
+  // noise product y = cB L xi after the factorisation (xi null: none);
+  // ypart: the panels' partial sums, (n / NB) rows of n
+  const double* xi;
+  double* y;
+  double* ypart;
+  double cB;
 };
 
 // Columns of the factorisation step starting at column k0: wide steps
@@ -1415,6 +1541,31 @@ hipError_t trailing(const CholCtx& c, hipStream_t s, int64_t k0, int64_t r0, int
   return hipGetLastError();
 }
 
+// The noise product's shares of the panels of the step at columns
+// k0 .. k0 + w - 1, once they are factored (the last panel of the matrix
+// has no rows below it).
+hipError_t noise_parts(const CholCtx& c, hipStream_t s, int64_t k0, int64_t w) {
+  if (!c.xi) return hipSuccess;
+  const int64_t p0 = k0 / NB;
+  const int64_t p1 = (k0 + w + NB - 1) / NB;
+  const int64_t np = ((p1 * NB < c.n) ? p1 : (c.n + NB - 1) / NB - 1) - p0;
+  const int64_t i0 = (p0 + 1) * NB / kNpRows * kNpRows;  // no row above stores
+  if (np > 0)
+    BD_LAUNCH("noise_part", noise_part_kernel,
+              dim3((unsigned)((c.n - i0 + kNpRows - 1) / kNpRows), (unsigned)np), dim3(kNpRows), 0,
+              s, c.A, c.ld, c.n, p0, i0, c.xi, c.ypart, c.cB);
+  return hipGetLastError();
+}
+
+// The ordered sums of the noise product, once every share is stored (all
+// on stream s by then).
+hipError_t diag_noise(const CholCtx& c, hipStream_t s) {
+  if (!c.xi) return hipSuccess;
+  BD_LAUNCH("noise_sum", noise_sum_kernel, dim3((unsigned)((c.n + NB - 1) / NB)), dim3(NB), 0, s,
+            c.A, c.ld, c.n, c.xi, c.ypart, c.y, c.cB);
+  return hipGetLastError();
+}
+
 // The panels of the step starting at k0: each later panel first receives
 // the update by the step's earlier panels (one tile column), then is
 // factored.  Returns the step width.
@@ -1443,8 +1594,13 @@ hipError_t factor_step(const CholCtx& c, hipStream_t s, int64_t k0, int64_t* wid
 // aux == nullptr everything runs on `s` in order.
 hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int64_t n, double* A,
                            int64_t ld, bd_precision_t prec, void* ws, DevState* st,
-                           int max_panels, int64_t wide_rows, bool tile_potrf) {
+                           int max_panels, int64_t wide_rows, bool tile_potrf, const double* xi,
+                           double* y, double cB, double* ypart) {
   CholCtx c;
+  c.xi = ypart ? xi : nullptr;
+  c.y = y;
+  c.ypart = ypart;
+  c.cB = cB;
   c.n = n;
   c.ld = ld;
   c.A = A;
@@ -1465,15 +1621,17 @@ hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int
     for (int64_t k = 0; k < n; k += w) {
       if ((e = factor_step(c, s, k, &w)) != hipSuccess) return e;
       if (k + w < n && (e = trailing(c, s, k, k + w, (int)w, kTilesAll, 0)) != hipSuccess) return e;
+      if ((e = noise_parts(c, s, k, w)) != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return diag_noise(c, s);
   }
   hipEvent_t ev_fork = ev[0], ev_panel = ev[1], ev_rest = ev[2], ev_next = ev[3];
   if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
   if ((e = hipStreamWaitEvent(aux, ev_fork, 0)) != hipSuccess) return e;
   if ((e = factor_step(c, aux, 0, &w)) != hipSuccess) return e;
   if ((e = hipEventRecord(ev_panel, aux)) != hipSuccess) return e;
-  for (int64_t k = 0; k + w < n;) {
+  int64_t k = 0;
+  for (; k + w < n;) {
     const int64_t r0 = k + w;
     const int nnext = (int)((step_width(c, r0) + NB - 1) / NB);  // panels of the next step
     // main: step k must be factored before it is applied
@@ -1490,11 +1648,14 @@ hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int
     if ((e = hipStreamWaitEvent(s, ev_next, 0)) != hipSuccess) return e;
     if ((e = trailing(c, s, k, r0, (int)w, kTilesRest, nnext)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev_rest, s)) != hipSuccess) return e;
+    // main: step k's noise shares, in the time it would wait for the chain
+    if ((e = noise_parts(c, s, k, w)) != hipSuccess) return e;
     k = r0;
     w = wn;
   }
   if ((e = hipStreamWaitEvent(s, ev_panel, 0)) != hipSuccess) return e;
-  return hipGetLastError();
+  if ((e = noise_parts(c, s, k, w)) != hipSuccess) return e;
+  return diag_noise(c, s);
 }
 
 namespace {
@@ -1508,6 +1669,7 @@ struct BatchCtx {
   bool mixed;
   int64_t step;  // columns per step, the same for every chain
   BatchTables* tb;
+  bool noise;    // fused noise product into each chain's y (xi, cB)
 };
 
 // The prefix array of the next launch from the workgroup counts of chains
@@ -1605,7 +1767,8 @@ hipError_t batch_factor_step(const BatchCtx& b, hipStream_t s, int64_t k0) {
       if (!ok) return hipErrorInvalidValue;
       if (!b.tb->record)
         BD_LAUNCH("panel_solve_batched", panel_solve_batched_kernel, dim3((unsigned)total),
-                  dim3(kPsThreads), 0, s, b.cd, pre, zp, k0, kp, batch_pidx(b, k0));
+                  dim3(kPsThreads), 0, s, b.cd, pre, zp, k0, kp, batch_pidx(b, k0),
+                  b.noise ? 1 : 0);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -1618,10 +1781,17 @@ hipError_t batch_factor_step(const BatchCtx& b, hipStream_t s, int64_t k0) {
 // every chain of the table at once.
 hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev[4],
                                    const ChainDesc* cd, const ChainDesc* cd_host, int count,
-                                   bd_precision_t prec, int panels, BatchTables* tb) {
+                                   bd_precision_t prec, int panels, BatchTables* tb, bool noise) {
   if (count <= 0) return hipSuccess;
   panels = (panels >= 4) ? 4 : 2;
-  BatchCtx b{cd, cd_host, count, prec == BD_PREC_MIXED, (int64_t)panels * NB, tb};
+  BatchCtx b{cd, cd_host, count, prec == BD_PREC_MIXED, (int64_t)panels * NB, tb, noise};
+  auto diag = [&]() {
+    if (noise && !tb->record)
+      BD_LAUNCH("noise_sum_batched", noise_sum_batched_kernel,
+                dim3((unsigned)((cd_host[0].n + NB - 1) / NB), 1, (unsigned)count), dim3(NB), 0, s,
+                cd);
+    return hipGetLastError();
+  };
   tb->cur = 0;
   const int64_t n = cd_host[0].n;  // the largest chain
   const int64_t w = b.step;
@@ -1632,7 +1802,7 @@ hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev
       if (k + w < n && (e = batch_trailing(b, s, k, k + w, (int)w, kTilesAll, 0)) != hipSuccess)
         return e;
     }
-    return hipGetLastError();
+    return diag();
   }
   // the recording pass takes the same path without launching anything
   const bool run = !tb->record;
@@ -1658,7 +1828,7 @@ hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev
     if ((e = record(ev_rest, s)) != hipSuccess) return e;
   }
   if ((e = wait(s, ev_panel)) != hipSuccess) return e;
-  return hipGetLastError();
+  return diag();
 }
 
 }  // namespace bd

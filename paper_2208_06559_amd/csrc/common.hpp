@@ -45,9 +45,16 @@ hipError_t launch_rpy_adjoint(hipStream_t s, const bd_params_t& p, const double*
 
 // cholesky.hip
 size_t cholesky_workspace_bytes(int64_t n, bd_precision_t prec);
+// With xi and ypart non-null the noise product y = cB L xi follows the
+// factorisation: one pass stores each panel's share of every row below it
+// in ypart (one row of n per panel, noise_part_bytes(n)), a second adds
+// them in panel order with the diagonal blocks' share (the sums, in their
+// order, of the ensemble's fused noise product).
 hipError_t launch_cholesky(hipStream_t s, hipStream_t aux, hipEvent_t ev[4], int64_t n, double* A,
                            int64_t ld, bd_precision_t prec, void* ws, DevState* st,
-                           int max_panels, int64_t wide_rows, bool tile_potrf);
+                           int max_panels, int64_t wide_rows, bool tile_potrf,
+                           const double* xi = nullptr, double* y = nullptr, double cB = 0.0,
+                           double* ypart = nullptr);
 
 // adjoint.hip
 size_t cholesky_adjoint_workspace_bytes(int64_t n);
@@ -79,6 +86,10 @@ hipError_t launch_predictor(hipStream_t s, const bd_params_t& p, const double* x
 // made `device` current), and the largest matrix order it holds.
 hipError_t brownian_scratch_init(int device, void** out);
 int64_t brownian_scratch_max_n();
+// The noise coefficient c_B (sqrt(2 dt), or sqrt(6 dt) for the paper's
+// uniform noise); the noise xi of one step.
+double noise_coeff(const bd_params_t& p);
+hipError_t launch_noise(hipStream_t s, const bd_params_t& p, int64_t step, double* xi);
 hipError_t launch_brownian_adjoint(hipStream_t s, const bd_params_t& p, const double* L,
                                    int64_t ld, const double* xi, const double* ybar,
                                    double* Lbar, int64_t ldb, double* xibar);
@@ -130,6 +141,10 @@ __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a -
 constexpr int kP32Tail = 64;
 // Its column stride: n rounded up to 16 bytes, so that columns stay aligned.
 __host__ __device__ inline int64_t p32_ld(int64_t n) { return (n + 3) / 4 * 4; }
+// The noise product's partial sums: one row of n per panel.
+inline size_t noise_part_bytes(int64_t n) {
+  return align_up(sizeof(double) * (size_t)((n + kNB - 1) / kNB) * (size_t)n, 256);
+}
 __host__ __device__ inline size_t p32_copy_bytes(int64_t n) {
   return align_up(sizeof(float) * ((size_t)p32_ld(n) * kMaxStep + kP32Tail), 256);
 }
@@ -155,8 +170,8 @@ struct ChainDesc {
   double* W;          // Cholesky: inverses of the diagonal sub-blocks
   float* P32[2];      // Cholesky MIXED: FP32 panel copies of alternate steps (p32_ld(n) x kMaxStep)
   double* xi;         // noise (n)
-  double* part;       // TRMV partial sums
-  double* y;          // Brownian displacement (n)
+  double* y;          // Brownian displacement (n), formed by the factorisation
+  double* ypart;      // its panels' partial sums (noise_part_bytes(n))
   double* xs;         // predictor / new positions (N x 3)
   void* cons;         // tension-solve workspace
   DevState* st;       // status of this chain
@@ -188,19 +203,21 @@ struct BatchTables {
 };
 // The chains of `cd` (device table, `cd_host` its host copy) ordered by
 // decreasing n, `count` of them; every chain is factored in place with the
-// schedule of launch_cholesky at `panels` (2 or 4) panels per step.
+// schedule of launch_cholesky at `panels` (2 or 4) panels per step; with
+// `noise`, each chain's y += cB L xi on the way (as launch_cholesky).
 hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev[4],
                                    const ChainDesc* cd, const ChainDesc* cd_host, int count,
-                                   bd_precision_t prec, int panels, BatchTables* tb);
-// Flattened grids of the assembly and the noise product: workgroups per
-// chain, and the launchers taking the prefix arrays over the table.
+                                   bd_precision_t prec, int panels, BatchTables* tb,
+                                   bool noise = false);
+// Flattened grid of the assembly: workgroups per chain, and the launcher
+// taking the prefix array over the table.
 int rpy_batched_blocks(int n_beads);
-int trmv_batched_blocks(int64_t n);
 hipError_t launch_rpy_assemble_batched(hipStream_t s, const ChainDesc* cd, int count,
                                        const int32_t* prefix, int blocks);
-hipError_t launch_brownian_batched(hipStream_t s, const ChainDesc* cd, int count, int64_t max_n,
-                                   int64_t step, const int32_t* tile_prefix, int tile_blocks,
-                                   const int64_t* d_step = nullptr);
+// Each chain's noise xi (d_step non-null: the step counter from device
+// memory).
+hipError_t launch_noise_batched(hipStream_t s, const ChainDesc* cd, int count, int64_t max_n,
+                                int64_t step, const int64_t* d_step = nullptr);
 hipError_t launch_predictor_batched(hipStream_t s, const ChainDesc* cd, int count, int max_beads);
 // Runs the tension solve of every chain; returns once every chain's
 // iteration has finished (polls the `count` states at `st`, which are

@@ -40,12 +40,19 @@ int main(int argc, char** argv) {
     if (prec == 1) {
       char* pc = ws + bd::align_up(sizeof(double) * bd::kNB * bd::kNB, 256);
       d.P32[0] = (float*)pc;
-      d.P32[1] = (float*)(pc + bd::align_up(sizeof(float) * (size_t)n * bd::kMaxStep, 256));
+      d.P32[1] = (float*)(pc + bd::p32_copy_bytes(n));
     }
     d.st = (bd::DevState*)calloc(1, sizeof(bd::DevState));
+    d.xi = (double*)calloc((size_t)n, sizeof(double));  // the fused noise product
+    d.y = (double*)calloc((size_t)n, sizeof(double));
+    d.ypart = (double*)calloc(1, bd::noise_part_bytes(n));
+    d.cB = 1.0;
     blocks.push_back(d.D);
     blocks.push_back(ws);
     blocks.push_back(d.st);
+    blocks.push_back(d.xi);
+    blocks.push_back(d.y);
+    blocks.push_back(d.ypart);
   }
   std::stable_sort(cd.begin(), cd.end(),
                    [](const bd::ChainDesc& a, const bd::ChainDesc& b) { return a.n > b.n; });
@@ -55,7 +62,7 @@ int main(int argc, char** argv) {
   bd::BatchTables tb;
   tb.record = true;
   hipError_t e = bd::launch_cholesky_batched(nullptr, aux, ev, cd.data(), cd.data(), count,
-                                             (bd_precision_t)prec, panels, &tb);
+                                             (bd_precision_t)prec, panels, &tb, true);
   const long recorded = g_emu_launches;
   tb.record = false;
   int32_t* tdev = (int32_t*)malloc(sizeof(int32_t) * (tb.host.size() + 1));
@@ -63,7 +70,7 @@ int main(int argc, char** argv) {
   tb.dev = tdev;
   if (e == hipSuccess)
     e = bd::launch_cholesky_batched(nullptr, aux, ev, cd.data(), cd.data(), count,
-                                    (bd_precision_t)prec, panels, &tb);
+                                    (bd_precision_t)prec, panels, &tb, true);
   if (recorded != 0 || tb.cur != tb.host.size()) e = hipErrorInvalidValue;
   free(tdev);
   printf("chains=%d prec=%d lookahead=%d panels=%d: status %d, %ld launches\n", count, prec,

@@ -5,10 +5,13 @@
 // lower 128 x 128 tile must receive the updates of columns 0 .. 128 J in
 // order, each exactly once, before its diagonal block is factored (tracked
 // on 64 x 64 sub-tiles, the finest tile a launch uses), and
-// every diagonal block is factored exactly once.
+// every diagonal block is factored exactly once.  In both precisions every
+// panel's share of the noise product y = L xi that ends the call must be
+// stored for every row below the panel, and every row of y formed from them.
 // Usage: chol_emu n ld prec(0 fp64, 1 mixed) max_panels(1|2|4) lookahead(0|1)
 //        [tile_potrf(0|1), default 1] [wide_rows, default 0: every step as
 //        wide as max_panels allows]
+#include <cstring>
 #include <map>
 #include <utility>
 
@@ -26,6 +29,8 @@ int64_t g_n = 0, g_ld = 0;
 std::map<std::pair<int64_t, int64_t>, int64_t> g_applied;  // tile -> columns applied
 std::map<int64_t, int> g_factored;                          // tile column -> times
 int g_errors = 0;
+
+const uint64_t kPartMark = 0x7ff8deadbeef0001ull, kYMark = 0x7ff8deadbeef0002ull;
 
 void fail(const char* what, int64_t a, int64_t b, int64_t c) {
   if (g_errors++ < 10) fprintf(stderr, "schedule error: %s (%lld, %lld, %lld)\n", what,
@@ -110,15 +115,42 @@ int main(int argc, char** argv) {
   memset(ws, 0, wsb);
   bd::DevState* st = (bd::DevState*)calloc(1, sizeof(bd::DevState));
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // the noise product: xi and y of exactly n doubles, the partial sums of
+  // exactly noise_part_bytes(n); y and the partial sums start as NaNs with
+  // payloads of their own, which no arithmetic on the factor can produce
+  double* xi = (double*)malloc(sizeof(double) * n);
+  double* y = (double*)malloc(sizeof(double) * n);
+  const size_t npb = bd::noise_part_bytes(n);
+  double* ypart = (double*)malloc(npb);
+  for (size_t i = 0; i < npb / sizeof(double); ++i) memcpy(&ypart[i], &kPartMark, 8);
+  for (int64_t i = 0; i < n; ++i) {
+    xi[i] = 0.5 + 0.25 * (double)((i * 7) % 13) - 1.5 * (double)(i % 2);
+    memcpy(&y[i], &kYMark, 8);
+  }
   const hipError_t e = bd::launch_cholesky(nullptr, use_aux ? (hipStream_t)0x1 : nullptr, ev, n, A,
-                                           ld, (bd_precision_t)prec, ws, st, sp, wide, tile);
+                                           ld, (bd_precision_t)prec, ws, st, sp, wide, tile, xi,
+                                           y, 1.0, ypart);
   if (prec == 0)
     for (int64_t J = 0; J * bd::NB < n; ++J)
       if (g_factored[J] != 1) fail("diagonal block not factored once", J, g_factored[J], 0);
+  // every panel's share of every row below it stored, and every row of y
+  // written without reading a share that was never stored (the emulated
+  // arithmetic is not the GPU's, so the values themselves are not checked)
+  if (e == hipSuccess) {
+    for (int64_t p = 0; (p + 1) * bd::NB < n; ++p)
+      for (int64_t i = (p + 1) * bd::NB; i < n; ++i)
+        if (memcmp(&ypart[p * n + i], &kPartMark, 8) == 0) fail("noise share not stored", p, i, 0);
+    for (int64_t i = 0; i < n; ++i)
+      if (memcmp(&y[i], &kYMark, 8) == 0 || memcmp(&y[i], &kPartMark, 8) == 0)
+        fail("noise product row not formed from stored shares", i, 0, 0);
+  }
   printf("n=%lld ld=%lld prec=%d max_panels=%d lookahead=%d tile_potrf=%d wide_rows=%lld: status %d, %ld launches, %d schedule errors\n",
          (long long)n, (long long)ld, prec, sp, use_aux, (int)tile, (long long)wide, e, g_emu_launches, g_errors);
   free(A);
   free(ws);
   free(st);
+  free(xi);
+  free(y);
+  free(ypart);
   return (e != hipSuccess || g_errors) ? 1 : 0;
 }
