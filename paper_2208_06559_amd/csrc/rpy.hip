@@ -1,11 +1,13 @@
 // RPY diffusion-tensor assembly (Eqs. 7-9), column-major D with ld.
 //
-// One work-item evaluates one 3x3 block D_ij (one sqrt, one divide chain)
-// and stores its three columns; consecutive work-items take consecutive
-// beads i, so each of the three column stores of a wavefront covers a
-// contiguous 64*24-byte run of one matrix column.  With BD_FILL_LOWER only
-// blocks with i >= j are touched and the diagonal block keeps its lower
-// part only.
+// A workgroup covers kRpyThreads consecutive matrix rows and kRpyJ
+// consecutive column beads j.  First its work-items evaluate the pairs
+// (i, j) of the beads i of those rows (one sqrt, one divide chain each)
+// into LDS; then each work-item takes one row rho = 3i + r and stores row r
+// of D_ij, one element in each of the columns 3j .. 3j + 2.  Consecutive
+// work-items take consecutive rows, so every store of a wavefront is one
+// contiguous 512-byte run of a column.  With BD_FILL_LOWER only blocks with
+// i >= j are touched and the diagonal block keeps its lower part only.
 #include "common.hpp"
 #include "profile.hpp"
 #include "rpy_device.hpp"
@@ -16,40 +18,57 @@ namespace {
 
 constexpr int kRpyThreads = 256;
 
-__device__ __forceinline__ void rpy_assemble_body(int bx, int j, const double* __restrict__ x,
+constexpr int kRpyJ = 4;                       // column beads per workgroup
+constexpr int kRpyBeads = kRpyThreads / 3 + 2;  // beads a run of kRpyThreads rows touches
+
+__device__ __forceinline__ void rpy_assemble_body(int bx, int by, const double* __restrict__ x,
                                                   double* __restrict__ D, int64_t ld, int N,
                                                   double hstar, double a, int fill_full) {
-  const int i = bx * kRpyThreads + threadIdx.x;  // row bead; j is the column bead
-  if (!fill_full && (bx + 1) * kRpyThreads <= j) return;  // block entirely above
-  if (i >= N) return;
-  if (!fill_full && i < j) return;
-  double blk[3][3];
-  if (i == j) {
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) blk[r][c] = (r == c) ? 1.0 : 0.0;
-  } else {
+  // per (bead of the block, column bead): cI, cRR and R = r_i - r_j
+  __shared__ double pair[kRpyJ][5][kRpyBeads];
+  const int64_t row0 = (int64_t)bx * kRpyThreads;
+  const int j0 = by * kRpyJ;
+  // rows entirely above the first column bead's diagonal block
+  if (!fill_full && row0 + kRpyThreads <= 3 * (int64_t)j0) return;
+  const int i0 = (int)(row0 / 3);
+  for (int q = threadIdx.x; q < kRpyBeads * kRpyJ; q += kRpyThreads) {
+    const int b = q / kRpyJ, u = q - kRpyJ * b, i = i0 + b, j = j0 + u;
+    if (i >= N || j >= N || i == j || (!fill_full && i < j)) continue;
     const double R0 = x[3 * i] - x[3 * j];
     const double R1 = x[3 * i + 1] - x[3 * j + 1];
     const double R2c = x[3 * i + 2] - x[3 * j + 2];
     const double R2 = R0 * R0 + R1 * R1 + R2c * R2c;
     double cI, cRR;
     rpy_coeffs(R2, hstar, a, cI, cRR);
-    const double Rv[3] = {R0, R1, R2c};
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) blk[r][c] = (r == c ? cI : 0.0) + cRR * Rv[r] * Rv[c];
+    pair[u][0][b] = cI;
+    pair[u][1][b] = cRR;
+    pair[u][2][b] = R0;
+    pair[u][3][b] = R1;
+    pair[u][4][b] = R2c;
   }
-  const int64_t row0 = 3 * (int64_t)i;
+  __syncthreads();
+  const int64_t rho = row0 + threadIdx.x;  // this work-item's row
+  if (rho >= 3 * (int64_t)N) return;
+  const int i = (int)(rho / 3), r = (int)(rho - 3 * (int64_t)i), b = i - i0;
+  for (int u = 0; u < kRpyJ; ++u) {
+    const int j = j0 + u;
+    if (j >= N || (!fill_full && i < j)) break;  // later beads j lie further right
+    double v[3];
+    if (i == j) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double* col = D + (3 * (int64_t)j + c) * ld + row0;
+      for (int c = 0; c < 3; ++c) v[c] = (r == c) ? 1.0 : 0.0;
+    } else {
+      const double cI = pair[u][0][b], cRR = pair[u][1][b];
+      const double Rv[3] = {pair[u][2][b], pair[u][3][b], pair[u][4][b]};
+      const double Rr = pair[u][2 + r][b];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c) v[c] = (r == c ? cI : 0.0) + cRR * Rr * Rv[c];
+    }
+    double* col = D + 3 * (int64_t)j * ld + rho;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
       if (!fill_full && i == j && r < c) continue;  // strict upper part of the diagonal block
-      col[r] = blk[r][c];
+      col[c * ld] = v[c];
     }
   }
 }
@@ -61,13 +80,14 @@ __global__ __launch_bounds__(kRpyThreads) void rpy_assemble_kernel(
 }
 
 // Ensembles: lower triangles, one flattened grid; chain c owns
-// rpy_batched_blocks(N_c) workgroups, (column bead j, row block bx) each.
+// rpy_batched_blocks(N_c) workgroups, (group of kRpyJ column beads, row
+// block bx) each.
 __global__ __launch_bounds__(kRpyThreads) void rpy_assemble_batched_kernel(
     const ChainDesc* __restrict__ cd, const int32_t* __restrict__ prefix, int count) {
   const int ci = find_chain(prefix, count, blockIdx.x);
   const ChainDesc& c = cd[ci];
   const int N = c.N;
-  const int nbx = (N + kRpyThreads - 1) / kRpyThreads;
+  const int nbx = (3 * N + kRpyThreads - 1) / kRpyThreads;
   const int local = blockIdx.x - prefix[ci];
   rpy_assemble_body(local % nbx, local / nbx, c.x, c.D, c.ld, N, c.hstar, c.a, 0);
 }
@@ -229,14 +249,14 @@ hipError_t launch_rpy_adjoint(hipStream_t s, const bd_params_t& p, const double*
 hipError_t launch_rpy_assemble(hipStream_t s, const bd_params_t& p, const double* x, double* D,
                                int64_t ld, int fill) {
   const int N = p.n_beads;
-  dim3 grid((N + kRpyThreads - 1) / kRpyThreads, N);
+  dim3 grid((3 * N + kRpyThreads - 1) / kRpyThreads, (N + kRpyJ - 1) / kRpyJ);
   BD_LAUNCH("rpy_assemble", rpy_assemble_kernel, grid, dim3(kRpyThreads), 0, s, x, D, ld, N, p.hstar,
                      p.a, fill == BD_FILL_FULL ? 1 : 0);
   return hipGetLastError();
 }
 
 int rpy_batched_blocks(int n_beads) {
-  return n_beads * ((n_beads + kRpyThreads - 1) / kRpyThreads);
+  return ((n_beads + kRpyJ - 1) / kRpyJ) * ((3 * n_beads + kRpyThreads - 1) / kRpyThreads);
 }
 
 hipError_t launch_rpy_assemble_batched(hipStream_t s, const ChainDesc* cd, int count,

@@ -154,3 +154,21 @@ def test_brownian_adjoint_accesses_in_bounds(baemu, N, pad, padb):
                        timeout=300)
     assert r.returncode == 0, (N, pad, padb, r.stderr[-3000:])
     assert "status 0" in r.stdout
+
+
+# The assembly (one chain, both fills; three chains through the batched
+# kernel): every element written where it belongs and nothing else, for
+# bead counts that leave ragged row blocks and column bead groups and
+# leading dimensions with padding.
+@pytest.fixture(scope="module")
+def rasemu(tmp_path_factory):
+    return _build(tmp_path_factory, "rpy_emu")
+
+
+@pytest.mark.parametrize("N,pad", [(1, 0), (2, 3), (5, 0), (85, 1), (86, 0), (171, 4), (300, 0)])
+@pytest.mark.parametrize("fill", [0, 1])
+def test_rpy_assemble_accesses_in_bounds(rasemu, N, pad, fill):
+    r = subprocess.run([rasemu, str(N), str(pad), str(fill)], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, (N, pad, fill, r.stderr[-3000:])
+    assert " 0 errors" in r.stdout
