@@ -1021,42 +1021,51 @@ __device__ __forceinline__ void noise_sum_body(int blk, const double* __restrict
                                                int64_t n, const double* __restrict__ xi,
                                                const double* __restrict__ ypart,
                                                double* __restrict__ y, double cB) {
+  // work-items r < NB add the panels' shares of row k + r, work-items NB + r
+  // its diagonal block's share, side by side; both sums keep their order
+  __shared__ double sdiag[NB];
   const int64_t k = (int64_t)blk * NB;
-  const int r = threadIdx.x;
-  if (k + r >= n) return;
+  const int half = threadIdx.x / NB, r = threadIdx.x - NB * half;
+  const bool live = k + r < n;
   // sixteen loads in flight at a time, the sums still in order
   constexpr int U = 16;
   double s = 0.0;
-  int p = 0;
-  for (; p + U <= blk; p += U) {
-    double v[U];
+  if (live && half == 0) {
+    int p = 0;
+    for (; p + U <= blk; p += U) {
+      double v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = ypart[(int64_t)(p + u) * n + k + r];
+      for (int u = 0; u < U; ++u) v[u] = ypart[(int64_t)(p + u) * n + k + r];
 #pragma unroll
-    for (int u = 0; u < U; ++u) s += v[u];
-  }
-  for (; p < blk; ++p) s += ypart[(int64_t)p * n + k + r];
-  const double* Akk = A + k * ld + k;
-  double sxi = 0.0;
-  int c = 0;
-  for (; c + U <= r + 1; c += U) {
-    double a[U], b[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      a[u] = Akk[(int64_t)(c + u) * ld + r];
-      b[u] = xi[k + c + u];
+      for (int u = 0; u < U; ++u) s += v[u];
     }
+    for (; p < blk; ++p) s += ypart[(int64_t)p * n + k + r];
+  } else if (live) {
+    const double* Akk = A + k * ld + k;
+    double sxi = 0.0;
+    int c = 0;
+    for (; c + U <= r + 1; c += U) {
+      double a[U], b[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) sxi += a[u] * b[u];
+      for (int u = 0; u < U; ++u) {
+        a[u] = Akk[(int64_t)(c + u) * ld + r];
+        b[u] = xi[k + c + u];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) sxi += a[u] * b[u];
+    }
+    for (; c <= r; ++c) sxi += Akk[(int64_t)c * ld + r] * xi[k + c];
+    sdiag[r] = sxi;
   }
-  for (; c <= r; ++c) sxi += Akk[(int64_t)c * ld + r] * xi[k + c];
-  y[k + r] = s + cB * sxi;
+  __syncthreads();
+  if (live && half == 0) y[k + r] = s + cB * sdiag[r];
 }
 
-__global__ __launch_bounds__(NB) void noise_sum_kernel(const double* __restrict__ A, int64_t ld,
-                                                       int64_t n, const double* __restrict__ xi,
-                                                       const double* __restrict__ ypart,
-                                                       double* __restrict__ y, double cB) {
+__global__ __launch_bounds__(2 * NB) void noise_sum_kernel(const double* __restrict__ A,
+                                                           int64_t ld, int64_t n,
+                                                           const double* __restrict__ xi,
+                                                           const double* __restrict__ ypart,
+                                                           double* __restrict__ y, double cB) {
   noise_sum_body(blockIdx.x, A, ld, n, xi, ypart, y, cB);
 }
 
@@ -1352,7 +1361,7 @@ __global__ __launch_bounds__(kPsThreads) void panel_solve_batched_kernel(
 }
 
 // Chain blockIdx.z's rows.
-__global__ __launch_bounds__(NB) void noise_sum_batched_kernel(const ChainDesc* __restrict__ cd) {
+__global__ __launch_bounds__(2 * NB) void noise_sum_batched_kernel(const ChainDesc* __restrict__ cd) {
   const ChainDesc& c = cd[blockIdx.z];
   if ((int64_t)blockIdx.x * NB >= c.n) return;
   noise_sum_body(blockIdx.x, c.D, c.ld, c.n, c.xi, c.ypart, c.y, c.cB);
@@ -1561,8 +1570,8 @@ hipError_t noise_parts(const CholCtx& c, hipStream_t s, int64_t k0, int64_t w) {
 // on stream s by then).
 hipError_t diag_noise(const CholCtx& c, hipStream_t s) {
   if (!c.xi) return hipSuccess;
-  BD_LAUNCH("noise_sum", noise_sum_kernel, dim3((unsigned)((c.n + NB - 1) / NB)), dim3(NB), 0, s,
-            c.A, c.ld, c.n, c.xi, c.ypart, c.y, c.cB);
+  BD_LAUNCH("noise_sum", noise_sum_kernel, dim3((unsigned)((c.n + NB - 1) / NB)), dim3(2 * NB), 0,
+            s, c.A, c.ld, c.n, c.xi, c.ypart, c.y, c.cB);
   return hipGetLastError();
 }
 
@@ -1788,8 +1797,8 @@ hipError_t launch_cholesky_batched(hipStream_t s, hipStream_t aux, hipEvent_t ev
   auto diag = [&]() {
     if (noise && !tb->record)
       BD_LAUNCH("noise_sum_batched", noise_sum_batched_kernel,
-                dim3((unsigned)((cd_host[0].n + NB - 1) / NB), 1, (unsigned)count), dim3(NB), 0, s,
-                cd);
+                dim3((unsigned)((cd_host[0].n + NB - 1) / NB), 1, (unsigned)count), dim3(2 * NB),
+                0, s, cd);
     return hipGetLastError();
   };
   tb->cur = 0;
