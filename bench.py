@@ -599,6 +599,13 @@ def main() -> int:
                    "ms_per_step": v[1] / args.profile_steps,
                    "share": v[1] / tot}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+        if "rpy_assemble" in brk:
+            # the assembly writes the lower triangle once: n(n+1)/2 doubles
+            ab = brk["rpy_assemble"]
+            a_s = ab["ms_per_step"] / ab["launches_per_step"] * 1e-3
+            a_by = n * (n + 1) / 2 * 8
+            ab["hbm"] = {"bytes_per_launch": a_by, "achieved_GBps": a_by / a_s / 1e9,
+                         "peak_GBps": PEAK_HBM, "frac": a_by / a_s / 1e9 / PEAK_HBM}
         if kern.startswith("syrk_update"):
             f32 = kern.endswith("f32")
             sched = schedule_in_use(h.tuning, n, pr)
