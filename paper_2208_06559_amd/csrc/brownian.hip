@@ -6,7 +6,10 @@
 // HBM: the lower triangle is cut into 256 x 256 tiles, one workgroup per
 // tile, one row per work-item, so every column access of a wavefront is a
 // contiguous 512-byte run.  Per-tile partial sums are reduced afterwards in
-// a fixed order (no floating-point atomics, bitwise reproducible).
+// a fixed order (no floating-point atomics, bitwise reproducible).  This is
+// the noise product of bd_brownian; inside a step the factorisation forms
+// y itself (panel by panel, in cholesky.hip), and this file supplies the
+// noise and its coefficient.
 #include "common.hpp"
 #include "profile.hpp"
 #include "philox.hpp"
