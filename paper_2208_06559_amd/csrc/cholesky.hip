@@ -2,8 +2,10 @@
 // column-major with leading dimension ld.
 //
 // For each panel of width NB starting at column k:
-//   1. potrf_diag   one workgroup factors the NB x NB diagonal block in LDS
-//                   (FP64) and writes the inverses of its four 32 x 32
+//   1. potrf_tile   one workgroup factors the NB x NB diagonal block (FP64,
+//                   16 x 16 tiles in registers, rank-16 updates on matrix
+//                   cores; potrf_diag, the register-tiled variant, on
+//                   request) and writes the inverses of its four 32 x 32
 //                   diagonal sub-blocks;
 //   2. panel_solve  L21 = A21 L11^-T by blocked forward substitution with
 //                   MFMA over row blocks (FP64); in MIXED mode it also stores
@@ -12,7 +14,13 @@
 //                   matrix with MFMA: FP64 operands/accumulators, or (MIXED)
 //                   FP32 operands with FP32 accumulation, subtracted into the
 //                   FP64 storage.
-// The diagonal blocks and panel solves stay FP64 in both modes.
+// The diagonal blocks and panel solves stay FP64 in both modes.  Panels
+// are applied in steps of up to four, with depth-1 lookahead on a second
+// stream (launch_cholesky).  Given the noise xi, the call also forms the
+// noise product y = c_B L xi: each panel's share of every row below it
+// (noise_part_kernel, launched beside the factorisation; for ensembles
+// inside the panel solve), then the shares' ordered sums with the
+// diagonal blocks' (noise_sum_kernel).
 //
 // MFMA operand convention (v_mfma_*_16x16x4): operand A holds A[i][k] in
 // lane i + 16k, operand B holds B[k][j] in lane j + 16k.  Result register r
@@ -1016,7 +1024,8 @@ __global__ __launch_bounds__(kNpRows) void noise_part_kernel(const double* __res
 // The noise product's sums, after the factorisation: row i of block b gets
 // y(i) = sum_{p < b} ypart(p, i) (the panels' shares, in panel order) +
 // cB sum_{c <= r} L(i, bNB + c) xi(bNB + c) (its diagonal block, r = i - bNB).
-// One thread per row; lanes read consecutive rows of one column.
+// Two work-items per row, one per sum; lanes read consecutive rows of one
+// column.
 __device__ __forceinline__ void noise_sum_body(int blk, const double* __restrict__ A, int64_t ld,
                                                int64_t n, const double* __restrict__ xi,
                                                const double* __restrict__ ypart,
@@ -1441,8 +1450,9 @@ struct CholCtx {
   int64_t wide_rows;  // four-panel steps only while more rows than this remain
   bool tile_potrf;    // diagonal blocks on matrix cores (else register tiles)
   DevState* st;
-  // noise product y = cB L xi after the factorisation (xi null: none);
-  // ypart: the panels' partial sums, (n / NB) rows of n
+  // noise product y = cB L xi (xi null: none): each step's panel shares
+  // beside the factorisation, their sums at its end; ypart: the panels'
+  // partial sums, (n / NB) rows of n
   const double* xi;
   double* y;
   double* ypart;
