@@ -165,7 +165,7 @@ def rasemu(tmp_path_factory):
     return _build(tmp_path_factory, "rpy_emu")
 
 
-@pytest.mark.parametrize("N,pad", [(1, 0), (2, 3), (5, 0), (85, 1), (86, 0), (171, 4), (300, 0)])
+@pytest.mark.parametrize("N,pad", [(1, 0), (2, 3), (5, 0), (85, 1), (86, 0), (171, 4), (300, 0), (1023, 2)])
 @pytest.mark.parametrize("fill", [0, 1])
 def test_rpy_assemble_accesses_in_bounds(rasemu, N, pad, fill):
     r = subprocess.run([rasemu, str(N), str(pad), str(fill)], capture_output=True, text=True,
